@@ -1,0 +1,187 @@
+"""Throughput of the fused coupled-LB step on one MI355X.
+
+One "step" is one time step of the whole coupled method (three LBs,
+moments, enthalpy inversion, finite differences, interface physics,
+collision and streaming) over the whole grid of one workload.  Default
+workload: freezing with impurities, 192^3 D3Q19, N = 4, float32 storage
+(the largest single-GPU configuration).  Inputs are generated in host
+memory, uploaded, and resident in HBM before timing starts.
+
+Prints one JSON line with MLUPS (million lattice updates per second, with
+conservation diagnostics every 100 steps inside the timed region), the
+HBM roofline of the step kernel (algorithmic bytes per launch over its
+average launch time, measured with HIP events on the solver's stream),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--workload impurities|droplet|compound|film]
+                  [--precision fp32|mixed|fp64] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS of coupled LB step + % HBM roofline; adjoint/forward cost ratio"
+KERNEL_SOURCES = ["lbf_step.h", "lbf_kernels.h", "lbf_lattice.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_22902_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_cell(dim: int, N: int, elt: int) -> int:
+    """Each population and lagged field read once and written once."""
+    Q = 9 if dim == 2 else 19
+    return 2 * elt * ((N + 2) * Q + (N + dim + 3))
+
+
+def measured_traffic(workload: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_case(workload: str, precision: str):
+    import synth
+    fn = synth.WORKLOADS[workload]
+    case = fn()
+    case["params"]["precision"] = precision
+    return case
+
+
+def describe(case) -> dict:
+    p = case["params"]
+    shape = (p["nx"], p["ny"]) + ((p["nz"],) if p["dim"] == 3 else ())
+    return {"workload": f"{case['name']} {'x'.join(map(str, shape))} D{p['dim']}Q{9 if p['dim'] == 2 else 19} "
+                        f"N={p['nphase']}",
+            "cells": int(p["nx"] * p["ny"] * (p["nz"] if p["dim"] == 3 else 1)),
+            "nphase": p["nphase"], "lattice": f"D{p['dim']}Q{9 if p['dim'] == 2 else 19}",
+            "storage": "f64" if p["precision"] == "fp64" else "f32",
+            "diag_interval": 100}
+
+
+def cpu_baseline(case, budget_s: float = 20.0) -> dict:
+    """The FP64 oracle on the same workload: initialisation, then whole
+    steps until about budget_s seconds of stepping have passed (at least
+    one step)."""
+    import oracle
+    o = oracle.Oracle(case["params"])
+    o.init_case(case)
+    ncell = case["T"].size
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / steps * (steps + 1) > 1.5 * budget_s:
+            break
+    return {"value": ncell * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} full step(s) of the same {ncell}-cell workload in float64 "
+                      f"({el:.1f} s, OpenMP over cells)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="impurities", choices=["impurities", "droplet", "compound", "film"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this solver's hot path is one kernel on one "
+              "device; multi-GPU slab decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_22902_amd import Solver
+
+    case = make_case(args.workload, args.precision)
+    prm = case["params"]
+    print(f"[bench] workload {case['name']} precision {args.precision} steps {args.steps} "
+          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+    s = Solver(prm)
+    s.init_case(case)
+    stream = s.stream
+    ncell = s.ncell
+    s.lbf_step(args.warmup)
+    torch.cuda.synchronize()
+
+    # Timed region 1 (the metric): K steps with diagnostics every 100 steps.
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record(stream)
+    done = 0
+    while done < args.steps:
+        n = min(100, args.steps - done)
+        s.lbf_step(n)
+        done += n
+        if n == 100:
+            s.lbf_diagnostics(check_nan=False)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_total = start.elapsed_time(stop)
+    print(f"[bench] timed {args.steps} steps: {ms_total:.2f} ms (host wall {wall * 1e3:.2f} ms)",
+          file=sys.stderr, flush=True)
+
+    # Timed region 2 (roofline): back-to-back step launches only.
+    k_steps = max(20, args.steps // 2)
+    start.record(stream)
+    s.lbf_step(k_steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms_kernel = start.elapsed_time(stop) / k_steps
+    diag = s.lbf_diagnostics(check_nan=False)
+    print(f"[bench] step kernel {ms_kernel * 1e3:.1f} us/launch; front {diag['front']:.4f} "
+          f"nonfinite {diag['nonfinite']}", file=sys.stderr, flush=True)
+
+    elt = 8 if args.precision == "fp64" else 4
+    bpc = algorithmic_bytes_per_cell(prm["dim"], prm["nphase"], elt)
+    bytes_per_launch = bpc * ncell
+    achieved = bytes_per_launch / (ms_kernel * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.precision)
+    ms_per_step = ms_total / args.steps
+    mlups = ncell * args.steps / (ms_total * 1e-3) / 1e6
+    dtype = {"fp32": "f32", "mixed": "f32 storage / f64 arithmetic", "fp64": "f64"}[args.precision]
+    out = {
+        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": describe(case),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "step_kernel", "kernel_us": round(ms_kernel * 1e3, 2),
+                     "bytes_per_cell": bpc, "mlups_kernel_only": round(ncell / (ms_kernel * 1e-3) / 1e6, 2)},
+    }
+    if not args.no_cpu_baseline:
+        del s
+        torch.cuda.synchronize()
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

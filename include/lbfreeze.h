@@ -1,0 +1,177 @@
+/*
+ * lbfreeze -- coupled lattice-Boltzmann solver for N-phase flow with
+ * liquid-solid phase change on one AMD MI355X (gfx950).
+ *
+ * Method: Huang, Zhan, Chai, Huang, Liu, "A diffuse-interface model for
+ * N-phase flows with liquid-solid phase change", arXiv:2603.22902.  One time
+ * step couples (Sec. 3)
+ *   - N conservative phase-field LBs g_{i,p} (conservative Allen-Cahn
+ *     equation, eq. (eq_ph), with the pairwise source R_p),
+ *   - the pressure-based flow LB f_i with the surface force F_s, the solid
+ *     penalty force and the volume-change source of eq. (fluid2),
+ *   - the total-enthalpy LB h_i with the enthalpy inversion of eq. (H),
+ * on D2Q9 (2D) or D3Q19 (3D).  Lateral axes are periodic; the wall-normal
+ * axis (y in 2D, z in 3D) ends in two faces, each a no-slip wall or an open
+ * (zero-pressure) face, with a Dirichlet or adiabatic thermal condition.
+ *
+ * Calling conventions
+ *   - Every function returns an lbf_status; nothing throws across the ABI.
+ *   - The caller owns every host array and the device buffer given to
+ *     lbf_create (size from lbf_state_bytes).  The library owns only the
+ *     opaque context, never allocates device memory and never frees caller
+ *     memory.
+ *   - Host arrays are float64 in C order [field][z][y][x] (nz = 1 in 2D),
+ *     whatever the device precision.
+ *   - lbf_step is asynchronous on the stream bound at lbf_create.  The
+ *     lbf_get_*, lbf_diagnostics and lbf_save_state calls synchronise that
+ *     stream before returning.
+ *   - A call that fails leaves the context unchanged unless stated otherwise;
+ *     lbf_last_error() then holds a message.
+ *   - Calls on one context must not overlap (one host thread at a time).
+ */
+#ifndef LBFREEZE_H
+#define LBFREEZE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBF_OK = 0,
+  LBF_EINVAL = -1,  /* invalid argument or parameter set            */
+  LBF_ENOMEM = -2,  /* buffer too small / size overflow            */
+  LBF_EDEVICE = -3, /* HIP runtime error                           */
+  LBF_ENOTSUP = -4, /* valid but unsupported combination           */
+  LBF_ENAN = -5,    /* non-finite state found by lbf_diagnostics   */
+  LBF_ESTATE = -6   /* call out of order (e.g. step before init)   */
+} lbf_status;
+
+enum { LBF_FP32 = 0, LBF_FP64 = 1, LBF_MIXED = 2 };
+enum { LBF_BC_WALL = 0, LBF_BC_OPEN = 1 };
+enum { LBF_TBC_DIRICHLET = 0, LBF_TBC_ADIABATIC = 1 };
+
+#define LBF_MAXP 4
+
+/* Problem definition, lattice units (dx = dt = 1, c_s^2 = 1/3).
+ * Phase p is described by liquid and solid values (eq. (eq2) mixes them
+ * with the solid fraction f_s).  A phase with freezes[p] = 0 must have equal
+ * liquid and solid values and zero latent heat.  Index [0] of the face
+ * arrays is the low face (coordinate 0, the substrate), [1] the high face. */
+typedef struct lbf_params {
+  int dim;             /* 2 (D2Q9) or 3 (D3Q19)                                   */
+  int nx, ny, nz;      /* cells; nz is ignored (taken as 1) in 2D                 */
+  int nphase;          /* N, 1..LBF_MAXP                                         */
+  int precision;       /* LBF_FP32: float32 storage and arithmetic; LBF_FP64:
+                          float64 throughout; LBF_MIXED: float32 storage,
+                          float64 arithmetic                                     */
+  int flow_bc[2];      /* LBF_BC_WALL / LBF_BC_OPEN per wall-normal face          */
+  int therm_bc[2];     /* LBF_TBC_DIRICHLET / LBF_TBC_ADIABATIC                   */
+  double T_face[2];    /* temperature of Dirichlet faces                          */
+  double rho_l[LBF_MAXP], rho_s[LBF_MAXP]; /* densities                            */
+  double mu_l[LBF_MAXP], mu_s[LBF_MAXP];   /* dynamic viscosities                  */
+  double lam_l[LBF_MAXP], lam_s[LBF_MAXP]; /* thermal conductivities               */
+  double cp_l[LBF_MAXP], cp_s[LBF_MAXP];   /* specific heats                       */
+  double latent[LBF_MAXP];                 /* latent heat L_p                      */
+  int freezes[LBF_MAXP];                   /* 1 if phase p can solidify            */
+  double sigma[LBF_MAXP][LBF_MAXP];        /* pairwise surface tension, symmetric  */
+  double cos_theta[LBF_MAXP][LBF_MAXP];    /* wetting at the low wall, cos of the
+                                              angle measured inside p; antisymmetric */
+  double eps;          /* interface width parameter epsilon (> 0)                 */
+  double tau_g;        /* phase-field relaxation time, mobility (tau_g-1/2)/3     */
+  double T_melt;       /* solidus = liquidus temperature                          */
+  double E_ref;        /* rho_ref C_p,ref of the enthalpy equilibrium (> 0)        */
+  double gravity[3];   /* body force G = rho g                                    */
+} lbf_params;
+
+typedef struct lbf_ctx lbf_ctx;
+
+/* Moment selection for lbf_get_moments; fields are written in this order,
+ * each as one [nz][ny][nx] plane (PHI: N planes, U: dim planes). */
+#define LBF_M_PHI (1u << 0)  /* order parameters phi_p                          */
+#define LBF_M_RHOH (1u << 1) /* total enthalpy rho H                            */
+#define LBF_M_T (1u << 2)    /* temperature                                     */
+#define LBF_M_FL (1u << 3)   /* liquid fraction f_l                             */
+#define LBF_M_RHO (1u << 4)  /* mixture density                                 */
+#define LBF_M_U (1u << 5)    /* velocity u                                      */
+#define LBF_M_P (1u << 6)    /* pressure                                        */
+#define LBF_M_MDOT (1u << 7) /* volume-change source mdot of eq. (fluid2)       */
+#define LBF_M_ALL 0xffu
+
+/* Validate a parameter set without touching any device (host only).  Checks
+ * sizes, N, relaxation times tau_f = 3 mu/rho + 1/2, tau_h = 3 lambda/E_ref
+ * + 1/2 and tau_g all above 1/2 in every phase state, positive densities and
+ * heat capacities, rho C_p >= (1 - w_0) E_ref (non-negative rest weight of
+ * the enthalpy equilibrium), consistency of non-freezing phases, symmetric
+ * sigma and antisymmetric cos_theta.  msg (may be NULL) receives the reason. */
+lbf_status lbf_check_params(const lbf_params* prm, char* msg, size_t msg_len);
+
+/* Device bytes the caller must provide to lbf_create for this problem:
+ * two population buffers ((N+2) Q values per cell), two lagged-field
+ * buffers (N + dim + 3 values per cell), one float64 staging plane and the
+ * reduction scratch of lbf_diagnostics. */
+lbf_status lbf_state_bytes(const lbf_params* prm, size_t* bytes);
+
+/* Bind a context to caller-owned device memory dev_buf (at least
+ * lbf_state_bytes, 256-byte aligned) on the current HIP device, and to the
+ * HIP stream hip_stream (a hipStream_t; NULL = default stream).  The state
+ * is undefined until lbf_init_fields. */
+lbf_status lbf_create(const lbf_params* prm, void* dev_buf, size_t bytes, void* hip_stream,
+                      lbf_ctx** out);
+
+/* Initial fields (Sec. 3, equilibrium start).  phi: [N][cells] with
+ * sum_p phi_p = 1 within 1e-12 and phi_p >= -1e-12; T: [cells]; u: [dim][cells]
+ * or NULL for rest; p: [cells] or NULL for zero.  Cells with T > T_melt start
+ * liquid, the rest solid; rho H follows from eq. (H); every population starts
+ * at its equilibrium.  Clears the sticky LBF_ENAN state. */
+lbf_status lbf_init_fields(lbf_ctx* ctx, const double* phi, const double* T, const double* u,
+                           const double* p);
+
+/* Advance nsteps >= 0 time steps (one fused kernel launch per step). */
+lbf_status lbf_step(lbf_ctx* ctx, int nsteps);
+
+/* Macroscopic fields at the current time level (moments of the current
+ * populations, inversion, and the flow macros u, p, mdot of Sec. 3), for the
+ * fields selected by mask, into out (float64, planes in LBF_M_* order). */
+lbf_status lbf_get_moments(lbf_ctx* ctx, unsigned mask, double* out);
+
+/* Current populations as float64 [(N+2)*Q][cells]: lattice 0 = f,
+ * 1..N = g_p, N+1 = h; direction order of the lattice tables in DESIGN notes
+ * (D2Q9: rest, +x, +y, -x, -y, then the four diagonals (+,+), (-,+), (-,-),
+ * (+,-); D3Q19: rest, +-x, +-y, +-z, then xy, xz, yz pairs). */
+lbf_status lbf_get_populations(lbf_ctx* ctx, double* out);
+
+/* Lagged fields as float64 [N + dim + 3][cells]: phi_p^{n-1}, f_s^{n-1},
+ * u^{n-1}, the velocity divergence D^{n-1} and (rho C_p T D)^{n-1}. */
+lbf_status lbf_get_aux(lbf_ctx* ctx, double* out);
+
+/* Conservation diagnostics at the current time level, float64:
+ * out[0..N) phase masses sum phi_p [f_s rho_p^s + (1-f_s) rho_p^l],
+ * out[N..2N) solid volumes sum f_s phi_p, out[2N..3N) volumes sum phi_p,
+ * out[3N] sum rho H, out[3N+1] max |sum_p phi_p - 1|, out[3N+2] front
+ * position sum f_s psi / (cells per wall layer) with psi the freezing
+ * phases' fraction, out[3N+3] 1 if any phi or rho H is non-finite.
+ * Returns LBF_ENAN (sticky until lbf_init_fields/lbf_load_state) if so. */
+lbf_status lbf_diagnostics(lbf_ctx* ctx, double* out);
+
+/* Opaque snapshot of the whole state (populations, lagged fields, step
+ * count).  bytes must equal lbf_snapshot_bytes. */
+lbf_status lbf_snapshot_bytes(const lbf_ctx* ctx, size_t* bytes);
+lbf_status lbf_save_state(lbf_ctx* ctx, void* host, size_t bytes);
+lbf_status lbf_load_state(lbf_ctx* ctx, const void* host, size_t bytes);
+
+/* Steps taken since lbf_init_fields (restored by lbf_load_state). */
+lbf_status lbf_step_count(const lbf_ctx* ctx, long long* steps);
+
+/* Release the context (not the caller's device buffer). NULL is a no-op. */
+lbf_status lbf_destroy(lbf_ctx* ctx);
+
+/* Last error message of this context ("" if none); valid until the next call. */
+const char* lbf_last_error(const lbf_ctx* ctx);
+const char* lbf_status_string(lbf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBFREEZE_H */

@@ -1,0 +1,349 @@
+// C ABI of the coupled LB freezing solver (include/lbfreeze.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/lbfreeze.h"
+#include "lbf_host.h"
+#include "lbf_ops.h"
+
+struct lbf_ctx {
+  lbf_params prm;
+  lbf::KParams kp;
+  lbf::Layout lay;
+  const lbf::Ops* ops;
+  int Q, nlat, naux, dim, N;
+  long long ncell;
+  char* base;
+  hipStream_t stream;
+  int device;
+  int cur;  // buffer index holding the current state
+  bool initialized, nan_flag;
+  long long steps;
+  std::string err;
+};
+
+namespace {
+
+constexpr uint64_t kSnapMagic = 0x315A4545524642ULL;  // "BFREEZ1"
+
+struct SnapHeader {
+  uint64_t magic;
+  int32_t dim, nx, ny, nz, nphase, precision;
+  uint64_t pop_bytes, aux_bytes;
+  int64_t steps;
+};
+
+lbf_status fail(lbf_ctx* c, lbf_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+lbf_status hip_fail(lbf_ctx* c, hipError_t e, const char* what) {
+  return fail(c, LBF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr, what)                 \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(c, e_, what); \
+  } while (0)
+
+void* pop_ptr(lbf_ctx* c, int k) { return c->base + c->lay.off_pop[k]; }
+void* aux_ptr(lbf_ctx* c, int k) { return c->base + c->lay.off_aux[k]; }
+double* stage_ptr(lbf_ctx* c) { return reinterpret_cast<double*>(c->base + c->lay.off_stage); }
+
+bool all_finite(const double* a, long long n) {
+  for (long long k = 0; k < n; ++k)
+    if (!isfinite(a[k])) return false;
+  return true;
+}
+
+// Copy a device array of n stored values (the state's precision) to a
+// float64 host array, plane by plane through the staging buffer.
+lbf_status read_back(lbf_ctx* c, const void* dev, long long nplanes, double* out) {
+  const long long nc = c->ncell;
+  if (c->prm.precision == LBF_FP64) {
+    HIPCHK(c, hipMemcpyAsync(out, dev, (size_t)nplanes * nc * 8, hipMemcpyDeviceToHost, c->stream),
+           "hipMemcpyAsync");
+  } else {
+    const float* src = static_cast<const float*>(dev);
+    for (long long k = 0; k < nplanes; ++k) {
+      HIPCHK(c, c->ops->widen(src + k * nc, stage_ptr(c), nc, c->stream), "widen");
+      HIPCHK(c, hipMemcpyAsync(out + k * nc, stage_ptr(c), (size_t)nc * 8, hipMemcpyDeviceToHost,
+                               c->stream),
+             "hipMemcpyAsync");
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return LBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbf_status lbf_check_params(const lbf_params* prm, char* msg, size_t msg_len) {
+  const std::string e = lbf::check_params(prm);
+  if (msg && msg_len) {
+    strncpy(msg, e.c_str(), msg_len - 1);
+    msg[msg_len - 1] = 0;
+  }
+  return e.empty() ? LBF_OK : LBF_EINVAL;
+}
+
+lbf_status lbf_state_bytes(const lbf_params* prm, size_t* bytes) {
+  if (!bytes) return LBF_EINVAL;
+  if (!lbf::check_params(prm).empty()) return LBF_EINVAL;
+  *bytes = lbf::make_layout(prm).total;
+  return LBF_OK;
+}
+
+lbf_status lbf_create(const lbf_params* prm, void* dev_buf, size_t bytes, void* hip_stream,
+                      lbf_ctx** out) {
+  if (!out) return LBF_EINVAL;
+  *out = nullptr;
+  if (!lbf::check_params(prm).empty()) return LBF_EINVAL;
+  const lbf::Layout lay = lbf::make_layout(prm);
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255)) return LBF_EINVAL;
+  if (bytes < lay.total) return LBF_ENOMEM;
+  const lbf::Ops* ops = prm->precision == LBF_FP64   ? lbf::ops_f64(prm->dim, prm->nphase)
+                        : prm->precision == LBF_MIXED ? lbf::ops_mix(prm->dim, prm->nphase)
+                                                      : lbf::ops_f32(prm->dim, prm->nphase);
+  if (!ops) return LBF_ENOTSUP;
+  lbf_ctx* c = new (std::nothrow) lbf_ctx();
+  if (!c) return LBF_ENOMEM;
+  c->prm = *prm;
+  if (prm->dim == 2) c->prm.nz = 1;
+  c->kp = lbf::make_kparams(&c->prm);
+  c->lay = lay;
+  c->ops = ops;
+  c->dim = prm->dim;
+  c->N = prm->nphase;
+  c->Q = lbf::lattice_q(prm->dim);
+  c->nlat = c->N + 2;
+  c->naux = c->N + c->dim + 3;
+  c->ncell = c->kp.ncell;
+  c->base = static_cast<char*>(dev_buf);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->cur = 0;
+  c->initialized = c->nan_flag = false;
+  c->steps = 0;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return LBF_EDEVICE;
+  }
+  *out = c;
+  return LBF_OK;
+}
+
+lbf_status lbf_init_fields(lbf_ctx* c, const double* phi, const double* T, const double* u,
+                           const double* p) {
+  if (!c) return LBF_EINVAL;
+  if (!phi || !T) return fail(c, LBF_EINVAL, "phi and T are required");
+  const long long nc = c->ncell;
+  const int N = c->N, d = c->dim;
+  if (!all_finite(phi, (long long)N * nc) || !all_finite(T, nc) ||
+      (u && !all_finite(u, (long long)d * nc)) || (p && !all_finite(p, nc)))
+    return fail(c, LBF_EINVAL, "initial fields must be finite");
+  for (long long k = 0; k < nc; ++k) {
+    double s = 0.0;
+    for (int q = 0; q < N; ++q) {
+      const double v = phi[(long long)q * nc + k];
+      if (v < -1e-12) return fail(c, LBF_EINVAL, "phi_p must be non-negative");
+      s += v;
+    }
+    if (fabs(s - 1.0) > 1e-12) return fail(c, LBF_EINVAL, "sum_p phi_p must equal 1 within 1e-12");
+  }
+  // Upload into the second population buffer (free until the first step).
+  const int scratch = 1 - c->cur;
+  double* f = static_cast<double*>(pop_ptr(c, scratch));
+  size_t off = 0;
+  HIPCHK(c, hipMemcpyAsync(f, phi, (size_t)N * nc * 8, hipMemcpyHostToDevice, c->stream), "upload phi");
+  off += (size_t)N * nc;
+  HIPCHK(c, hipMemcpyAsync(f + off, T, (size_t)nc * 8, hipMemcpyHostToDevice, c->stream), "upload T");
+  off += nc;
+  if (u) {
+    HIPCHK(c, hipMemcpyAsync(f + off, u, (size_t)d * nc * 8, hipMemcpyHostToDevice, c->stream),
+           "upload u");
+    off += (size_t)d * nc;
+  }
+  if (p) HIPCHK(c, hipMemcpyAsync(f + off, p, (size_t)nc * 8, hipMemcpyHostToDevice, c->stream), "upload p");
+  const int dst = c->cur;
+  HIPCHK(c, c->ops->init(c->kp, f, u ? 1 : 0, p ? 1 : 0, pop_ptr(c, dst), aux_ptr(c, dst), c->stream),
+         "init kernel");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->initialized = true;
+  c->nan_flag = false;
+  c->steps = 0;
+  c->err.clear();
+  return LBF_OK;
+}
+
+lbf_status lbf_step(lbf_ctx* c, int nsteps) {
+  if (!c) return LBF_EINVAL;
+  if (nsteps < 0) return fail(c, LBF_EINVAL, "nsteps must be >= 0");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  for (int s = 0; s < nsteps; ++s) {
+    const int a = c->cur, b = 1 - c->cur;
+    HIPCHK(c, c->ops->step(pop_ptr(c, a), pop_ptr(c, b), aux_ptr(c, a), aux_ptr(c, b), nullptr, 0, c->kp,
+                           c->stream, false),
+           "step kernel");
+    c->cur = b;
+    ++c->steps;
+  }
+  return LBF_OK;
+}
+
+lbf_status lbf_get_moments(lbf_ctx* c, unsigned mask, double* out) {
+  if (!c) return LBF_EINVAL;
+  if (!out) return fail(c, LBF_EINVAL, "out is NULL");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  const int N = c->N, d = c->dim;
+  const long long nc = c->ncell;
+  // field ids: phi_p (0..N-1), rhoH N, T N+1, f_l N+2, rho N+3, u N+4.., p N+4+d, mdot N+5+d
+  int ids[16], nf = 0;
+  if (mask & LBF_M_PHI)
+    for (int q = 0; q < N; ++q) ids[nf++] = q;
+  if (mask & LBF_M_RHOH) ids[nf++] = N;
+  if (mask & LBF_M_T) ids[nf++] = N + 1;
+  if (mask & LBF_M_FL) ids[nf++] = N + 2;
+  if (mask & LBF_M_RHO) ids[nf++] = N + 3;
+  if (mask & LBF_M_U)
+    for (int a = 0; a < d; ++a) ids[nf++] = N + 4 + a;
+  if (mask & LBF_M_P) ids[nf++] = N + 4 + d;
+  if (mask & LBF_M_MDOT) ids[nf++] = N + 5 + d;
+  const int a = c->cur;
+  for (int k = 0; k < nf; ++k) {
+    HIPCHK(c, c->ops->step(pop_ptr(c, a), nullptr, aux_ptr(c, a), nullptr, stage_ptr(c), ids[k], c->kp,
+                           c->stream, true),
+           "moments kernel");
+    HIPCHK(c, hipMemcpyAsync(out + (long long)k * nc, stage_ptr(c), (size_t)nc * 8, hipMemcpyDeviceToHost,
+                             c->stream),
+           "hipMemcpyAsync");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return LBF_OK;
+}
+
+lbf_status lbf_get_populations(lbf_ctx* c, double* out) {
+  if (!c) return LBF_EINVAL;
+  if (!out) return fail(c, LBF_EINVAL, "out is NULL");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  return read_back(c, pop_ptr(c, c->cur), (long long)c->nlat * c->Q, out);
+}
+
+lbf_status lbf_get_aux(lbf_ctx* c, double* out) {
+  if (!c) return LBF_EINVAL;
+  if (!out) return fail(c, LBF_EINVAL, "out is NULL");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  return read_back(c, aux_ptr(c, c->cur), c->naux, out);
+}
+
+lbf_status lbf_diagnostics(lbf_ctx* c, double* out) {
+  if (!c) return LBF_EINVAL;
+  if (!out) return fail(c, LBF_EINVAL, "out is NULL");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  double* part = reinterpret_cast<double*>(c->base + c->lay.off_part);
+  double* dout = reinterpret_cast<double*>(c->base + c->lay.off_out);
+  HIPCHK(c, c->ops->diag(c->kp, pop_ptr(c, c->cur), aux_ptr(c, c->cur), part, dout, c->stream), "diag kernel");
+  HIPCHK(c, hipMemcpyAsync(out, dout, (size_t)c->lay.nv * 8, hipMemcpyDeviceToHost, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (out[3 * c->N + 3] != 0.0) c->nan_flag = true;
+  if (c->nan_flag) return fail(c, LBF_ENAN, "non-finite order parameter or enthalpy in the state");
+  return LBF_OK;
+}
+
+lbf_status lbf_snapshot_bytes(const lbf_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return LBF_EINVAL;
+  *bytes = sizeof(SnapHeader) + c->lay.pop_bytes + c->lay.aux_bytes;
+  return LBF_OK;
+}
+
+lbf_status lbf_save_state(lbf_ctx* c, void* host, size_t bytes) {
+  if (!c) return LBF_EINVAL;
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  size_t need;
+  lbf_snapshot_bytes(c, &need);
+  if (!host || bytes != need) return fail(c, LBF_EINVAL, "snapshot buffer has the wrong size");
+  SnapHeader h;
+  memset(&h, 0, sizeof h);
+  h.magic = kSnapMagic;
+  h.dim = c->prm.dim;
+  h.nx = c->prm.nx;
+  h.ny = c->prm.ny;
+  h.nz = c->prm.nz;
+  h.nphase = c->N;
+  h.precision = c->prm.precision;
+  h.pop_bytes = c->lay.pop_bytes;
+  h.aux_bytes = c->lay.aux_bytes;
+  h.steps = c->steps;
+  char* dst = static_cast<char*>(host);
+  memcpy(dst, &h, sizeof h);
+  HIPCHK(c, hipMemcpyAsync(dst + sizeof h, pop_ptr(c, c->cur), c->lay.pop_bytes, hipMemcpyDeviceToHost,
+                           c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipMemcpyAsync(dst + sizeof h + c->lay.pop_bytes, aux_ptr(c, c->cur), c->lay.aux_bytes,
+                           hipMemcpyDeviceToHost, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return LBF_OK;
+}
+
+lbf_status lbf_load_state(lbf_ctx* c, const void* host, size_t bytes) {
+  if (!c) return LBF_EINVAL;
+  size_t need;
+  lbf_snapshot_bytes(c, &need);
+  if (!host || bytes != need) return fail(c, LBF_EINVAL, "snapshot has the wrong size");
+  SnapHeader h;
+  memcpy(&h, host, sizeof h);
+  if (h.magic != kSnapMagic || h.dim != c->prm.dim || h.nx != c->prm.nx || h.ny != c->prm.ny ||
+      h.nz != c->prm.nz || h.nphase != c->N || h.precision != c->prm.precision ||
+      h.pop_bytes != c->lay.pop_bytes || h.aux_bytes != c->lay.aux_bytes || h.steps < 0)
+    return fail(c, LBF_EINVAL, "snapshot does not match this context");
+  const char* src = static_cast<const char*>(host);
+  HIPCHK(c, hipMemcpyAsync(pop_ptr(c, c->cur), src + sizeof h, c->lay.pop_bytes, hipMemcpyHostToDevice,
+                           c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipMemcpyAsync(aux_ptr(c, c->cur), src + sizeof h + c->lay.pop_bytes, c->lay.aux_bytes,
+                           hipMemcpyHostToDevice, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  c->steps = h.steps;
+  c->initialized = true;
+  c->nan_flag = false;
+  return LBF_OK;
+}
+
+lbf_status lbf_step_count(const lbf_ctx* c, long long* steps) {
+  if (!c || !steps) return LBF_EINVAL;
+  *steps = c->steps;
+  return LBF_OK;
+}
+
+lbf_status lbf_destroy(lbf_ctx* c) {
+  delete c;
+  return LBF_OK;
+}
+
+const char* lbf_last_error(const lbf_ctx* c) { return c ? c->err.c_str() : ""; }
+
+const char* lbf_status_string(lbf_status s) {
+  switch (s) {
+    case LBF_OK: return "ok";
+    case LBF_EINVAL: return "invalid argument";
+    case LBF_ENOMEM: return "buffer too small";
+    case LBF_EDEVICE: return "HIP runtime error";
+    case LBF_ENOTSUP: return "not supported";
+    case LBF_ENAN: return "non-finite state";
+    case LBF_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Type-erased entry points of the kernels for one (dim, N, precision).
+// Each precision lives in its own translation unit (float64 is compiled
+// without floating-point contraction); the C ABI picks a table at run time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbf_lattice.h"
+
+namespace lbf {
+
+struct Ops {
+  hipError_t (*step)(const void* pin, void* pout, const void* ain, void* aout, double* mout,
+                     int mfield, const KParams& P, hipStream_t s, bool moments);
+  hipError_t (*init)(const KParams& P, const double* fields, int has_u, int has_p, void* pop,
+                     void* aux, hipStream_t s);
+  hipError_t (*diag)(const KParams& P, const void* pop, const void* aux, double* part,
+                     double* out, hipStream_t s);
+  hipError_t (*widen)(const void* in, double* out, long long n, hipStream_t s);
+};
+
+// dim 2 or 3, nphase 1..4; NULL if not built.  f32: float32 storage and
+// arithmetic; f64: float64 throughout; mix: float32 storage, float64
+// arithmetic.
+const Ops* ops_f32(int dim, int nphase);
+const Ops* ops_f64(int dim, int nphase);
+const Ops* ops_mix(int dim, int nphase);
+
+}  // namespace lbf
+
+// Instantiation of one precision's table (used by the two kernel units).
+#define LBF_DEFINE_OPS(NAME, ST, RT)                                                                 \
+  namespace lbf {                                                                                \
+  template <int DIM, int NP>                                                                     \
+  struct OpsImpl_##NAME {                                                                        \
+    static hipError_t step(const void* pin, void* pout, const void* ain, void* aout,             \
+                           double* mout, int mfield, const KParams& P, hipStream_t s,            \
+                           bool moments) {                                                       \
+      StepArgs<ST> a;                                                                            \
+      a.pin = static_cast<const ST*>(pin);                                                       \
+      a.pout = static_cast<ST*>(pout);                                                           \
+      a.ain = static_cast<const ST*>(ain);                                                       \
+      a.aout = static_cast<ST*>(aout);                                                           \
+      a.mout = mout;                                                                             \
+      a.mfield = mfield;                                                                         \
+      a.P = P;                                                                                   \
+      return launch_step<DIM, NP, ST, RT>(a, s, moments);                                            \
+    }                                                                                            \
+    static hipError_t init(const KParams& P, const double* fields, int has_u, int has_p,         \
+                           void* pop, void* aux, hipStream_t s) {                                \
+      return launch_init<DIM, NP, ST>(P, fields, has_u, has_p, static_cast<ST*>(pop),            \
+                                      static_cast<ST*>(aux), s);                                 \
+    }                                                                                            \
+    static hipError_t diag(const KParams& P, const void* pop, const void* aux, double* part,     \
+                           double* out, hipStream_t s) {                                         \
+      return launch_diag<DIM, NP, ST, RT>(P, static_cast<const ST*>(pop),                        \
+                                          static_cast<const ST*>(aux), part, out, s);            \
+    }                                                                                            \
+    static hipError_t widen(const void* in, double* out, long long n, hipStream_t s) {           \
+      return launch_widen<ST>(static_cast<const ST*>(in), out, n, s);                            \
+    }                                                                                            \
+    static constexpr Ops ops = {&step, &init, &diag, &widen};                                    \
+  };                                                                                             \
+  const Ops* NAME(int dim, int nphase) {                                                         \
+    static const Ops* table[2][4] = {                                                            \
+        {&OpsImpl_##NAME<2, 1>::ops, &OpsImpl_##NAME<2, 2>::ops, &OpsImpl_##NAME<2, 3>::ops,     \
+         &OpsImpl_##NAME<2, 4>::ops},                                                            \
+        {&OpsImpl_##NAME<3, 1>::ops, &OpsImpl_##NAME<3, 2>::ops, &OpsImpl_##NAME<3, 3>::ops,     \
+         &OpsImpl_##NAME<3, 4>::ops}};                                                           \
+    if (dim < 2 || dim > 3 || nphase < 1 || nphase > 4) return nullptr;                          \
+    return table[dim - 2][nphase - 1];                                                           \
+  }                                                                                              \
+  }

@@ -1,0 +1,693 @@
+// The fused coupled-LB time step of arXiv:2603.22902, Sec. 3, as the
+// barrier-separated phases of one HIP kernel.
+//
+// Storage (structure of arrays, x fastest): populations
+// pop[(lattice*Q + i)*ncell + cell], lattice 0 = f, 1..N = g_p, N+1 = h,
+// holding post-stream values (the state at the start of a step); lagged
+// fields aux[k*ncell + cell] = phi_p^{n-1} (N), f_s^{n-1}, u^{n-1} (DIM),
+// D^{n-1} (velocity divergence used by the previous step's sources) and
+// q^{n-1} = (rho C_p T D)^{n-1}.  A step reads buffers "in" and writes "out"
+// (push streaming: each cell writes its post-collision values to x + c_i).
+//
+// Work decomposition: a block owns a lateral tile of TX (x TY in 3D) cells
+// and marches along the wall-normal axis (y in 2D, z in 3D) over a chunk of
+// layers.  An LDS ring of three layers holds, for the tile plus a one-cell
+// lateral halo, the fields the finite differences need (phi_p, f_s, rho,
+// u^{n-1}) and each cell's rho H and T.  Each layer is filled once (the
+// halo cells' moments are recomputed by neighbouring blocks); ghost layers
+// outside the wall-normal faces are derived from the boundary layer in LDS.
+//
+// Every phase is a __host__ __device__ function of an explicit thread index
+// so that the same code also runs in the host emulator used by the CPU
+// tests; the device kernel and the emulator only differ in how they
+// sequence the phases around the block barriers.
+#pragma once
+
+#include <math.h>
+
+#include "lbf_lattice.h"
+
+namespace lbf {
+
+// S: storage type of populations and lagged fields; R: arithmetic type.
+template <int DIM_, int NP_, typename S_, typename R_, int TX_, int TY_>
+struct Cfg {
+  static constexpr int DIM = DIM_, NP = NP_, TX = TX_, TY = TY_;
+  using S = S_;
+  using R = R_;
+  using L = Lat<DIM_>;
+  static constexpr int Q = L::Q;
+  static constexpr int NT = TX * TY;
+  static constexpr int LX = TX + 2;
+  static constexpr int LY = (DIM == 3) ? TY + 2 : 1;
+  static constexpr int F = LX * LY;  // footprint cells per layer
+  static constexpr int NAUX = NP + DIM + 3;
+  static constexpr int A_FS = NP, A_U = NP + 1, A_DIV = NP + 1 + DIM, A_Q = NP + 2 + DIM;
+  static_assert(DIM == 3 || TY == 1, "2D tiles are one row of cells");
+};
+
+template <class C>
+struct Smem {
+  typename C::R phi[3][C::NP][C::F];
+  typename C::R fs[3][C::F];
+  typename C::R rho[3][C::F];
+  typename C::R u[3][C::DIM][C::F];
+  double rhoH[3][C::F];
+  double T[3][C::F];
+};
+
+template <typename S>
+struct StepArgs {
+  const S* pin;
+  S* pout;
+  const S* ain;
+  S* aout;
+  double* mout;  // moments mode: one float64 plane
+  int mfield;    // moments mode: field id (phi_p, rhoH, T, f_l, rho, u, p, mdot)
+  int ntx, nty;  // lateral tiles
+  int chunk;     // layers per block
+  int nblocks;
+  KParams P;
+};
+
+struct BlockPos {
+  int tx0, ty0, w0, w1;
+};
+
+__host__ __device__ inline int imod(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+__host__ __device__ inline int slot(int w) { return imod(w, 3); }
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of logical blocks so that neighbouring tiles share an L2.
+__host__ __device__ inline int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int x = b % 8, k = b / 8;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <class C>
+__host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, int b) {
+  const int Lg = xcd_remap(b, a.nblocks);
+  const int ntiles = a.ntx * a.nty;
+  const int chunk_id = Lg / ntiles, tile = Lg % ntiles;
+  BlockPos bp;
+  bp.tx0 = (tile % a.ntx) * C::TX;
+  bp.ty0 = (tile / a.ntx) * C::TY;
+  bp.w0 = chunk_id * a.chunk;
+  const int w1 = bp.w0 + a.chunk;
+  bp.w1 = w1 < a.P.nwn ? w1 : a.P.nwn;
+  return bp;
+}
+
+// Mixture law, eq. (eq2).
+template <typename R, int NP>
+__host__ __device__ inline R mixture(const R* phi, R fs, const double* xs, const double* xl) {
+  R x = R(0);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) x += fs * phi[p] * R(xs[p]) + (R(1) - fs) * phi[p] * R(xl[p]);
+  return x;
+}
+
+// Enthalpy inversion, eq. (H), always in float64.  Solid and liquid states
+// are the eq. (eq2) mixtures at f_s = 1 and 0, the volumetric latent heat is
+// sum_p phi_p rho_p^l L_p, solidus = liquidus = T_melt; an empty mushy range
+// (no freezing phase present) counts as liquid.
+template <int NP, typename R>
+__host__ __device__ inline void invert(const KParams& P, const R* phi, double rhoH, double& T,
+                                       double& fl) {
+  double rs = 0, rl = 0, cs = 0, cl = 0, Lv = 0;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const double ph = double(phi[p]);
+    rs += ph * P.rho_s[p];
+    rl += ph * P.rho_l[p];
+    cs += ph * P.cp_s[p];
+    cl += ph * P.cp_l[p];
+    Lv += ph * P.rho_l[p] * P.latent[p];
+  }
+  const double Tm = P.T_melt;
+  const double Es = rs * cs * Tm;
+  const double El = rl * cl * Tm + Lv;
+  if (rhoH < Es) {
+    fl = 0.0;
+    T = rhoH / (rs * cs);
+  } else if (rhoH > El) {
+    fl = 1.0;
+    T = Tm + (rhoH - El) / (rl * cl);
+  } else {
+    fl = (El > Es) ? (rhoH - Es) / (El - Es) : 1.0;
+    T = Tm;
+  }
+}
+
+__host__ __device__ inline double gprime(double x) { return 2.0 * x * (1.0 - x) * (1.0 - 2.0 * x); }
+__host__ __device__ inline float gprime(float x) { return 2.0f * x * (1.0f - x) * (1.0f - 2.0f * x); }
+
+// ---------------------------------------------------------------------------
+// Fill: moments of one footprint cell of a real layer into the LDS ring.
+// phi_p = sum_i g_{i,p} / (1 - D^{n-1}/2); rho H = sum_i h_i + q^{n-1}/2.
+// ---------------------------------------------------------------------------
+template <class C>
+__host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
+                                          const BlockPos& bp, int f, int w) {
+  using R = typename C::R;
+  constexpr int Q = C::Q, NP = C::NP;
+  const KParams& P = a.P;
+  const int lx = f % C::LX, ly = f / C::LX;
+  long long lat = imod(bp.tx0 + lx - 1, P.nx);
+  if (C::DIM == 3) lat += (long long)imod(bp.ty0 + ly - 1, P.ny) * P.nx;
+  const long long nc = P.ncell, cell = (long long)w * P.area + lat;
+  const R div = R(a.ain[C::A_DIV * nc + cell]);
+  const R qv = R(a.ain[C::A_Q * nc + cell]);
+  const int s = slot(w);
+  R phi[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    R sum = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sum += R(a.pin[((1 + p) * Q + i) * nc + cell]);
+    phi[p] = sum / (R(1) - R(0.5) * div);
+    sm.phi[s][p][f] = phi[p];
+  }
+  double sh = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) sh += double(a.pin[((NP + 1) * Q + i) * nc + cell]);
+  const double rhoH = sh + 0.5 * double(qv);
+  double T, fl;
+  invert<NP>(P, phi, rhoH, T, fl);
+  const R fs = R(1.0 - fl);
+  sm.fs[s][f] = fs;
+  sm.rho[s][f] = mixture<R, NP>(phi, fs, P.rho_s, P.rho_l);
+#pragma unroll
+  for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = R(a.ain[(C::A_U + d) * nc + cell]);
+  sm.rhoH[s][f] = rhoH;
+  sm.T[s][f] = T;
+}
+
+// Ghost layer beyond a wall-normal face (w = -1 or w = nwn), from the
+// boundary layer already in LDS.  At the low face of a wall the order
+// parameters follow the geometric wetting rule
+//   phi_p(ghost) = phi_p + (4/eps) sum_{q != p} phi_p phi_q cos(theta_pq);
+// everything else is copied, except u^{n-1}, which is mirrored at walls
+// (zero on the face) and copied at open faces.
+template <class C>
+__host__ __device__ inline void fill_ghost(const StepArgs<typename C::S>& a, Smem<C>& sm, int f,
+                                           int w) {
+  using R = typename C::R;
+  constexpr int NP = C::NP;
+  const KParams& P = a.P;
+  const int face = (w < 0) ? 0 : 1;
+  const int sb = slot(face == 0 ? 0 : P.nwn - 1), s = slot(w);
+  if (face == 0 && P.flow_bc[0] == BC_WALL) {
+    R pb[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) pb[p] = sm.phi[sb][p][f];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      R acc = R(0);
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        if (q != p) acc += pb[p] * pb[q] * R(P.cth[p][q]);
+      sm.phi[s][p][f] = pb[p] + R(P.four_eps) * acc;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) sm.phi[s][p][f] = sm.phi[sb][p][f];
+  }
+  sm.fs[s][f] = sm.fs[sb][f];
+  sm.rho[s][f] = sm.rho[sb][f];
+  const R sgn = (P.flow_bc[face] == BC_WALL) ? R(-1) : R(1);
+#pragma unroll
+  for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = sgn * sm.u[sb][d][f];
+  sm.rhoH[s][f] = sm.rhoH[sb][f];
+  sm.T[s][f] = sm.T[sb][f];
+}
+
+template <class C>
+__host__ __device__ inline void fill_layer_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
+                                                const BlockPos& bp, int f, int w) {
+  if (w < 0 || w >= a.P.nwn)
+    fill_ghost<C>(a, sm, f, w);
+  else
+    fill_cell<C>(a, sm, bp, f, w);
+}
+
+// Push of one post-collision population: x + c_i inside the domain gets it;
+// a link leaving through a wall-normal face instead stores the face's value
+// for the opposite (incoming) direction at this cell.
+template <class C>
+__host__ __device__ inline long long push_index(const KParams& P, int i, int gx, int gy, int w,
+                                                int& face) {
+  using L = typename C::L;
+  const int tw = w + L::cw(i);
+  if (tw < 0 || tw >= P.nwn) {
+    face = tw < 0 ? 0 : 1;
+    return -1;
+  }
+  face = -1;
+  long long lat = imod(gx + L::cl0(i), P.nx);
+  if (C::DIM == 3) lat += (long long)imod(gy + L::cl1(i), P.ny) * P.nx;
+  return (long long)tw * P.area + lat;
+}
+
+// ---------------------------------------------------------------------------
+// Process: steps 3-7 of the time step for the interior cell of thread tid in
+// layer w.  MOMENTS = true writes one macroscopic field instead of the
+// collision.
+// ---------------------------------------------------------------------------
+template <class C, bool MOMENTS>
+__host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
+                                             const BlockPos& bp, int tid, int w) {
+  using R = typename C::R;
+  using ST = typename C::S;  // storage type
+  using L = typename C::L;
+  constexpr int Q = C::Q, NP = C::NP, DIM = C::DIM;
+  const KParams& P = a.P;
+  const int tx = tid % C::TX, ty = tid / C::TX;
+  const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
+  if (gx >= P.nx) return;
+  if (DIM == 3 && gy >= P.ny) return;
+  const long long nc = P.ncell;
+  const long long lat = (DIM == 3) ? (long long)gy * P.nx + gx : (long long)gx;
+  const long long cell = (long long)w * P.area + lat;
+  const int fc = (DIM == 3) ? (ty + 1) * C::LX + tx + 1 : tx + 1;
+  const int s0 = slot(w);
+
+  // Own moments (identical to the values the neighbours see).
+  R phi[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) phi[p] = sm.phi[s0][p][fc];
+  const R fs = sm.fs[s0][fc];
+  const R rho = sm.rho[s0][fc];
+  const double rhoH = sm.rhoH[s0][fc];
+  const double Td = sm.T[s0][fc];
+  const R T = R(Td);
+  R psi = R(0);
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    if (P.freezes[p]) psi += phi[p];
+  const R mu = mixture<R, NP>(phi, fs, P.mu_s, P.mu_l);
+  const R lam = mixture<R, NP>(phi, fs, P.lam_s, P.lam_l);
+  const R cp = mixture<R, NP>(phi, fs, P.cp_s, P.cp_l);
+  R uprev[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) uprev[d] = sm.u[s0][d][fc];
+
+  // Step 3: isotropic central differences at time n,
+  // grad X = 3 sum_i w_i c_i X(x+c_i), lap X = 6 sum_i w_i [X(x+c_i) - X(x)].
+  R gphi[NP][DIM], lphi[NP], grho[DIM], gfp[NP][DIM], gu[DIM];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    lphi[p] = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gphi[p][d] = gfp[p][d] = R(0);
+  }
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) grho[d] = gu[d] = R(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int sn = slot(w + L::cw(i));
+    const int fn = fc + L::cl0(i) + L::cl1(i) * C::LX;
+    const R wi = wgt<R, DIM>(i);
+    const R fsn = sm.fs[sn][fn];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const R X = sm.phi[sn][p][fn];
+      const R t = wi * X;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if (L::c(i, d) > 0) gphi[p][d] += t;
+        if (L::c(i, d) < 0) gphi[p][d] -= t;
+      }
+      lphi[p] += wi * (X - phi[p]);
+      if (P.freezes[p]) {
+        const R tf = wi * (fsn * X);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if (L::c(i, d) > 0) gfp[p][d] += tf;
+          if (L::c(i, d) < 0) gfp[p][d] -= tf;
+        }
+      }
+    }
+    const R tr = wi * sm.rho[sn][fn];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const R tu = wi * sm.u[sn][d][fn];
+      if (L::c(i, d) > 0) {
+        grho[d] += tr;
+        gu[d] += tu;
+      }
+      if (L::c(i, d) < 0) {
+        grho[d] -= tr;
+        gu[d] -= tu;
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    lphi[p] *= R(6);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      gphi[p][d] *= R(3);
+      gfp[p][d] *= R(3);
+    }
+  }
+  R Ddiv = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    grho[d] *= R(3);
+    Ddiv += R(3) * gu[d];
+  }
+
+  // Step 4: interface physics of Sec. 2.  Pairwise normals via the quotient
+  // rule, v = phi_q grad phi_p - phi_p grad phi_q, |v| regularised by 1e-12.
+  R nrm[NP][NP][DIM];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int q = p + 1; q < NP; ++q) {
+      R v[DIM], vv = R(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        v[d] = phi[q] * gphi[p][d] - phi[p] * gphi[q][d];
+        vv += v[d] * v[d];
+      }
+      const R inv = R(1) / sqrt(vv + R(1e-24));
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        nrm[p][q][d] = v[d] * inv;
+        nrm[q][p][d] = -nrm[p][q][d];
+      }
+    }
+  R Rp[NP][DIM], mup[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Rp[p][d] = R(0);
+    R bulk = R(0), gterm = R(0);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      if (q == p) continue;
+      const R sc = R(4) * phi[p] * phi[q] / R(P.eps);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) Rp[p][d] += sc * nrm[p][q][d];
+      bulk += R(2) * R(P.beta[p][q]) * (gprime(phi[p]) - gprime(phi[p] + phi[q]));
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      if (q == p) continue;
+      gterm += R(P.kpq[p][q]) * lphi[q];
+    }
+    mup[p] = bulk - gterm;
+  }
+  R F[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    R fsd = R(0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) fsd += mup[p] * gphi[p][d];
+    F[d] = fsd + rho * R(P.grav[d]);
+  }
+
+  // Step 5: flow macros.
+  R fpop[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) fpop[i] = R(a.pin[i * nc + cell]);
+  R mom[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) mom[d] = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (L::c(i, d) > 0) mom[d] += fpop[i];
+      if (L::c(i, d) < 0) mom[d] -= fpop[i];
+    }
+  const R ws = fs * psi;
+  R u[DIM], rhoa[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const R us = (mom[d] + R(0.5) * F[d]) / rho;
+    const R acc = ws * (R(0) - us);
+    u[d] = us + R(0.5) * acc;
+    rhoa[d] = rho * acc;
+  }
+  // mdot = -(1/rho) sum_{p freezing} (rho_p^s - rho_p^l) D(f_s phi_p)/Dt
+  R msum = R(0);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    if (!P.freezes[p]) continue;
+    const R phip = R(a.ain[p * nc + cell]);
+    const R fsp = R(a.ain[C::A_FS * nc + cell]);
+    R ug = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ug += u[d] * gfp[p][d];
+    msum += R(P.rho_s[p] - P.rho_l[p]) * (fs * phi[p] - fsp * phip + ug);
+  }
+  const R mdot = -msum / rho;
+  R ugr = R(0), uu = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    ugr += u[d] * grho[d];
+    uu += u[d] * u[d];
+  }
+  const R S = rho * mdot + ugr;
+  // Forcing F_i = w_i [S + 3 c.(F + rho a) + 9/2 (c c - I/3) : Lambda],
+  // Lambda = u F + F u + (2/d) rho cs2 S I.
+  R Lam[DIM][DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int e = 0; e < DIM; ++e)
+      Lam[d][e] = u[d] * F[e] + F[d] * u[e] +
+                  (d == e ? R(2.0 / DIM) * rho * R(1.0 / 3.0) * S : R(0));
+  R Fi[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R cF = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (L::c(i, d) > 0) cF += F[d] + rhoa[d];
+      if (L::c(i, d) < 0) cF -= F[d] + rhoa[d];
+    }
+    R qq = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int e = 0; e < DIM; ++e)
+        qq += (R(L::c(i, d) * L::c(i, e)) - (d == e ? R(1.0 / 3.0) : R(0))) * Lam[d][e];
+    Fi[i] = wgt<R, DIM>(i) * (S + R(3) * cF + R(4.5) * qq);
+  }
+  const R tau_f = R(3) * mu / rho + R(0.5);
+  R sf = R(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) sf += fpop[i];
+  const R w0 = wgt<R, DIM>(0);
+  const R s0u = w0 * (R(0) + R(0) - R(1.5) * uu);
+  const R pr = R(1.0 / 3.0) / (R(1) - w0) * (sf + R(0.5) * S + (tau_f - R(0.5)) * Fi[0] + rho * s0u);
+
+  if (MOMENTS) {
+    const int k = a.mfield;
+    double v = 0.0;
+    if (k < NP) v = double(phi[k]);
+    else if (k == NP) v = rhoH;
+    else if (k == NP + 1) v = Td;
+    else if (k == NP + 2) {
+      double t2, fl2;
+      invert<NP>(P, phi, rhoH, t2, fl2);
+      v = fl2;
+    } else if (k == NP + 3) v = double(rho);
+    else if (k < NP + 4 + DIM) v = double(u[k - NP - 4]);
+    else if (k == NP + 4 + DIM) v = double(pr);
+    else v = double(mdot);
+    a.mout[cell] = v;
+    return;
+  }
+
+  // Step 6-7: collisions and push streaming.
+  // Flow LB: f^eq_0 = 3p (w_0 - 1) + rho s_0, f^eq_i = 3p w_i + rho s_i.
+  const R itf = R(1) / tau_f;
+  const R sfac = R(1) - R(0.5) / tau_f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R cu = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (L::c(i, d) > 0) cu += u[d];
+      if (L::c(i, d) < 0) cu -= u[d];
+    }
+    const R wi = wgt<R, DIM>(i);
+    const R si = wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+    const R fe = (i == 0) ? R(3) * pr * (w0 - R(1)) + rho * si : R(3) * pr * wi + rho * si;
+    const R post = fpop[i] - (fpop[i] - fe) / tau_f + sfac * Fi[i];
+    int face;
+    const long long t = push_index<C>(P, i, gx, gy, w, face);
+    if (t >= 0) {
+      a.pout[i * nc + t] = ST(post);
+    } else {
+      const int ib = L::opp(i);
+      R val;
+      if (P.flow_bc[face] == BC_WALL) {
+        val = post;  // halfway bounce-back
+      } else {
+        // open face: ghost at pressure 0 with this cell's u and rho
+        R cub = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if (L::c(ib, d) > 0) cub += u[d];
+          if (L::c(ib, d) < 0) cub -= u[d];
+        }
+        const R wb = wgt<R, DIM>(ib);
+        const R sb = wb * (R(3) * cub + R(4.5) * cub * cub - R(1.5) * uu);
+        const R feb = R(3) * pr * wb + rho * sb;
+        val = rho * sb + (R(1) - itf) * (fpop[ib] - feb);
+      }
+      a.pout[ib * nc + cell] = ST(val);
+    }
+  }
+
+  // Phase-field LBs: g^eq = w_i phi (1 + 3 c.u),
+  // G = w_i [3 c.(phi u - phi^{n-1} u^{n-1}) + c.R_p] + w_i phi D.
+  const R tg = R(P.tau_g);
+  const R gfac = R(1) - R(0.5) / tg;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const R phip = R(a.ain[p * nc + cell]);
+    R dpu[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) dpu[d] = phi[p] * u[d] - phip * uprev[d];
+    R gpop[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) gpop[i] = R(a.pin[((1 + p) * Q + i) * nc + cell]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R cd = R(0), cr = R(0), cu = R(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if (L::c(i, d) > 0) {
+          cd += dpu[d];
+          cr += Rp[p][d];
+          cu += u[d];
+        }
+        if (L::c(i, d) < 0) {
+          cd -= dpu[d];
+          cr -= Rp[p][d];
+          cu -= u[d];
+        }
+      }
+      const R wi = wgt<R, DIM>(i);
+      const R Gi = wi * (R(3) * cd + cr) + wi * phi[p] * Ddiv;
+      const R ge = wi * phi[p] * (R(1) + R(3) * cu);
+      const R post = gpop[i] - (gpop[i] - ge) / tg + gfac * Gi;
+      int face;
+      const long long t = push_index<C>(P, i, gx, gy, w, face);
+      const int l = 1 + p;
+      if (t >= 0) {
+        a.pout[(l * Q + i) * nc + t] = ST(post);
+      } else {
+        const int ib = L::opp(i);
+        R val;
+        if (P.flow_bc[face] == BC_WALL) {
+          val = post;
+        } else {
+          R cub = R(0);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            if (L::c(ib, d) > 0) cub += u[d];
+            if (L::c(ib, d) < 0) cub -= u[d];
+          }
+          const R geb = wgt<R, DIM>(ib) * phi[p] * (R(1) + R(3) * cub);
+          val = geb + (R(1) - R(1) / tg) * (gpop[ib] - geb);
+        }
+        a.pout[(l * Q + ib) * nc + cell] = ST(val);
+      }
+    }
+  }
+
+  // Total-enthalpy LB: h^eq_0 = rhoH - E_ref T + w_0 (E_ref T - 3/2 rho C_p T u.u),
+  // h^eq_i = w_i [E_ref T + rho C_p T (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)],
+  // H_i = w_i rho C_p T D, tau_h = 3 lambda / E_ref + 1/2.  The rest
+  // population is updated in float64 (it carries the latent heat offset).
+  const R rhocp = rho * cp;
+  const R Eref = R(P.E_ref);
+  const R tau_h = R(3) * lam / Eref + R(0.5);
+  const R hfac = R(1) - R(0.5) / tau_h;
+  R hpop[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) hpop[i] = R(a.pin[((NP + 1) * Q + i) * nc + cell]);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R wi = wgt<R, DIM>(i);
+    R post;
+    R he;
+    if (i == 0) {
+      const double Er = P.E_ref;
+      const double rc = double(rhocp);
+      const double he0 =
+          rhoH - Er * Td + double(w0) * (Er * Td - 1.5 * rc * Td * double(uu));
+      const double H0 = double(wi) * rc * Td * double(Ddiv);
+      const double td = double(tau_h);
+      const double h0 = double(hpop[0]);
+      post = R(h0 - (h0 - he0) / td + (1.0 - 0.5 / td) * H0);
+      he = R(he0);
+    } else {
+      R cu = R(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if (L::c(i, d) > 0) cu += u[d];
+        if (L::c(i, d) < 0) cu -= u[d];
+      }
+      he = wi * (Eref * T + rhocp * T * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+      const R Hi = wi * rhocp * T * Ddiv;
+      post = hpop[i] - (hpop[i] - he) / tau_h + hfac * Hi;
+    }
+    int face;
+    const long long t = push_index<C>(P, i, gx, gy, w, face);
+    if (t >= 0) {
+      a.pout[((NP + 1) * Q + i) * nc + t] = ST(post);
+    } else {
+      const int ib = L::opp(i);
+      R val;
+      if (P.flow_bc[face] == BC_WALL && P.therm_bc[face] == TBC_ADIABATIC) {
+        val = post;
+      } else {
+        const R Tg = (P.therm_bc[face] == TBC_DIRICHLET) ? R(2) * R(P.T_face[face]) - T : T;
+        R ug[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ug[d] = (P.flow_bc[face] == BC_OPEN) ? u[d] : R(0);
+        R cub = R(0), cuc = R(0), ugug = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          if (L::c(ib, d) > 0) {
+            cub += ug[d];
+            cuc += u[d];
+          }
+          if (L::c(ib, d) < 0) {
+            cub -= ug[d];
+            cuc -= u[d];
+          }
+          ugug += ug[d] * ug[d];
+        }
+        const R wb = wgt<R, DIM>(ib);
+        const R hg = wb * (Eref * Tg + rhocp * Tg * (R(3) * cub + R(4.5) * cub * cub - R(1.5) * ugug));
+        const R heb = wb * (Eref * T + rhocp * T * (R(3) * cuc + R(4.5) * cuc * cuc - R(1.5) * uu));
+        val = hg + (R(1) - R(1) / tau_h) * (hpop[ib] - heb);
+      }
+      a.pout[((NP + 1) * Q + ib) * nc + cell] = ST(val);
+    }
+  }
+
+  // Lagged fields for the next step.
+#pragma unroll
+  for (int p = 0; p < NP; ++p) a.aout[p * nc + cell] = ST(phi[p]);
+  a.aout[C::A_FS * nc + cell] = ST(fs);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) a.aout[(C::A_U + d) * nc + cell] = ST(u[d]);
+  a.aout[C::A_DIV * nc + cell] = ST(Ddiv);
+  a.aout[C::A_Q * nc + cell] = ST(rhocp * T * Ddiv);
+}
+
+}  // namespace lbf

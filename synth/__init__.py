@@ -173,12 +173,14 @@ def impurities(seed_k=4, n=192, radius=64.0, steps=10000, precision="fp32"):
     with gas properties.  Impurity radii r_A, r_B ~ U[8, 16], centres uniform
     in the droplet, at least r + eps inside its surface and above the wall,
     and at least eps apart."""
+    if radius < 2.0 * (16.0 + EPS) + 2.0:
+        raise ValueError("droplet radius too small to hold the impurities")
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + seed_k))
     rA, rB = (float(v) for v in rng.uniform(8.0, 16.0, size=2))
     c0 = np.array([n / 2, n / 2, 0.0])
 
     def draw(r, others):
-        while True:
+        for _ in range(100000):
             cand = np.array([rng.uniform(c0[0] - radius, c0[0] + radius),
                              rng.uniform(c0[1] - radius, c0[1] + radius),
                              rng.uniform(0.0, radius)])
@@ -189,6 +191,7 @@ def impurities(seed_k=4, n=192, radius=64.0, steps=10000, precision="fp32"):
             if any(np.linalg.norm(cand - oc) < r + orr + EPS for oc, orr in others):
                 continue
             return cand
+        raise ValueError("could not place the impurities")
 
     cA = draw(rA, [])
     cB = draw(rB, [(cA, rA)])
@@ -235,7 +238,9 @@ def small(dim=2, shape=(70, 37), nphase=2, precision="fp64", seed_k=11,
     else:
         r = np.sqrt((x - L / 2) ** 2 + (y - shape[1] / 2) ** 2 + z ** 2)
     drop = tanh_in(R - r)
-    if nphase == 2:
+    if nphase == 1:
+        phi = np.ones((1,) + drop.shape)
+    elif nphase == 2:
         phi = np.stack([drop, 1.0 - drop])
     else:
         core = tanh_in(0.5 * R - r)

@@ -1,0 +1,108 @@
+"""CPU-side checks of the HIP library: it loads, exports the whole C ABI,
+validates parameters on the host, and its kernels, run by the host
+emulator, agree with the oracle.  No GPU needed."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import emulator
+from parity_util import TOL, compare_moments, rel_err
+from paper_2603_22902_amd import lbfreeze
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lbfreeze.h")
+
+
+def test_library_exports_every_declared_symbol():
+    decl = set(re.findall(r"\b(lbf_[a-z_]+)\s*\(", open(HEADER).read()))
+    assert len(decl) >= 15
+    L = lbfreeze.lib()
+    missing = [n for n in decl if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _ok(case):
+    return lbfreeze.lbf_check_params(case["params"])
+
+
+def test_check_params_accepts_the_workloads():
+    for fn in (synth.film, synth.droplet, synth.compound):
+        s, msg = _ok(fn())
+        assert s == 0, msg
+    s, msg = _ok(synth.impurities(n=136))
+    assert s == 0, msg
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda p: p.update(dim=4), "dim"),
+    (lambda p: p.update(nphase=5), "nphase"),
+    (lambda p: p.update(ny=1), "wall-normal"),
+    (lambda p: p.update(tau_g=0.5), "tau_g"),
+    (lambda p: p["mu_l"].__setitem__(0, 0.0), "viscosit"),
+    (lambda p: (p["cp_l"].__setitem__(1, 1.0), p["cp_s"].__setitem__(1, 1.0)), "rho C_p"),
+    (lambda p: p["rho_s"].__setitem__(1, 0.5), "does not freeze"),
+    (lambda p: p["sigma"][0].__setitem__(1, 7.0), "symmetric"),
+    (lambda p: p["cos_theta"][0].__setitem__(1, 0.5), "antisymmetric"),
+    (lambda p: p.update(E_ref=float("nan")), "E_ref"),
+    (lambda p: p.update(precision=7), "precision"),
+])
+def test_check_params_rejects(mutate, needle):
+    case = synth.droplet(n=32, radius=8.0)
+    prm = case["params"]
+    for k in ("mu_l", "cp_l", "cp_s", "rho_s"):
+        prm[k] = list(prm[k])
+    prm["sigma"] = [list(r) for r in prm["sigma"]]
+    prm["cos_theta"] = [list(r) for r in prm["cos_theta"]]
+    mutate(prm)
+    s, msg = lbfreeze.lbf_check_params(prm)
+    assert s == lbfreeze.LBF_EINVAL and needle in msg, msg
+
+
+def test_state_bytes_covers_both_buffers():
+    case = synth.impurities(n=136)
+    nb = lbfreeze.lbf_state_bytes(case["params"])
+    nc = 136 ** 3
+    assert nb >= 2 * 4 * nc * (6 * 19 + 4 + 3 + 3) + 8 * nc
+    assert nb < 2 * 4 * nc * (6 * 19 + 10) + 8 * nc + (1 << 20)
+
+
+# ----- host emulator of the step kernel against the oracle ---------------
+EMU_CASES = [
+    (2, (37, 29), 2, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic"), 1e-3),
+    (2, (131, 9), 3, "fp64", ("wall", "open"), ("dirichlet", "dirichlet"), 1e-3),
+    (2, (5, 12), 1, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic"), 1e-3),
+    (3, (21, 13, 11), 4, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic"), 1e-3),
+    (3, (34, 9, 6), 2, "fp64", ("wall", "open"), ("adiabatic", "dirichlet"), 1e-3),
+    (2, (37, 29), 3, "fp32", ("wall", "wall"), ("dirichlet", "adiabatic"), 1e-6),
+    (3, (21, 13, 11), 4, "fp32", ("wall", "open"), ("dirichlet", "dirichlet"), 1e-6),
+    (3, (21, 13, 11), 3, "mixed", ("wall", "wall"), ("dirichlet", "adiabatic"), 1e-6),
+]
+
+
+@pytest.mark.skipif(not emulator.available(), reason="emulator not built")
+@pytest.mark.parametrize("spec", EMU_CASES, ids=lambda s: f"d{s[0]}_N{s[2]}_{s[3]}_{s[4][1]}")
+def test_emulated_kernel_matches_oracle(spec):
+    dim, shape, N, prec, fbc, tbc, noise = spec
+    case = synth.stress(synth.small(dim=dim, shape=shape, nphase=N, precision=prec, flow_bc=fbc,
+                                    therm_bc=tbc, theta_deg=70.0, gravity=(1e-6, -2e-6, 0.0)),
+                        phi_noise=noise)
+    n = 12
+    pop, aux, mom = emulator.run(case, n)
+    o = oracle.Oracle(case["params"])
+    o.init_case(case)
+    o.step(n)
+    errs, bad = compare_moments(mom, o.moments(), prec)
+    assert not bad, errs
+    assert rel_err(pop, o.populations(), prec) <= TOL[prec]
+    assert rel_err(aux, o.aux(), prec) <= TOL[prec]
+
+
+@pytest.mark.skipif(not os.path.exists(emulator.SAN_PATH), reason="sanitizer driver not built")
+def test_emulated_kernel_under_address_sanitizer():
+    r = subprocess.run([emulator.SAN_PATH], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "0 with non-finite output" in r.stdout
