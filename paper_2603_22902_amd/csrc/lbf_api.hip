@@ -56,6 +56,7 @@ lbf_status hip_fail(lbf_ctx* c, hipError_t e, const char* what) {
 void* pop_ptr(lbf_ctx* c, int k) { return c->base + c->lay.off_pop[k]; }
 void* aux_ptr(lbf_ctx* c, int k) { return c->base + c->lay.off_aux[k]; }
 double* stage_ptr(lbf_ctx* c) { return reinterpret_cast<double*>(c->base + c->lay.off_stage); }
+const lbf::KParams* kp_ptr(lbf_ctx* c) { return reinterpret_cast<const lbf::KParams*>(c->base + c->lay.off_kp); }
 
 bool all_finite(const double* a, long long n) {
   for (long long k = 0; k < n; ++k)
@@ -133,7 +134,10 @@ lbf_status lbf_create(const lbf_params* prm, void* dev_buf, size_t bytes, void* 
   c->cur = 0;
   c->initialized = c->nan_flag = false;
   c->steps = 0;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipMemcpyAsync(c->base + lay.off_kp, &c->kp, sizeof(c->kp), hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return LBF_EDEVICE;
   }
@@ -174,7 +178,7 @@ lbf_status lbf_init_fields(lbf_ctx* c, const double* phi, const double* T, const
   }
   if (p) HIPCHK(c, hipMemcpyAsync(f + off, p, (size_t)nc * 8, hipMemcpyHostToDevice, c->stream), "upload p");
   const int dst = c->cur;
-  HIPCHK(c, c->ops->init(c->kp, f, u ? 1 : 0, p ? 1 : 0, pop_ptr(c, dst), aux_ptr(c, dst), c->stream),
+  HIPCHK(c, c->ops->init(c->kp, kp_ptr(c), f, u ? 1 : 0, p ? 1 : 0, pop_ptr(c, dst), aux_ptr(c, dst), c->stream),
          "init kernel");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   c->initialized = true;
@@ -191,7 +195,7 @@ lbf_status lbf_step(lbf_ctx* c, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     const int a = c->cur, b = 1 - c->cur;
     HIPCHK(c, c->ops->step(pop_ptr(c, a), pop_ptr(c, b), aux_ptr(c, a), aux_ptr(c, b), nullptr, 0, c->kp,
-                           c->stream, false),
+                           kp_ptr(c), c->stream, false),
            "step kernel");
     c->cur = b;
     ++c->steps;
@@ -220,7 +224,7 @@ lbf_status lbf_get_moments(lbf_ctx* c, unsigned mask, double* out) {
   const int a = c->cur;
   for (int k = 0; k < nf; ++k) {
     HIPCHK(c, c->ops->step(pop_ptr(c, a), nullptr, aux_ptr(c, a), nullptr, stage_ptr(c), ids[k], c->kp,
-                           c->stream, true),
+                           kp_ptr(c), c->stream, true),
            "moments kernel");
     HIPCHK(c, hipMemcpyAsync(out + (long long)k * nc, stage_ptr(c), (size_t)nc * 8, hipMemcpyDeviceToHost,
                              c->stream),
@@ -250,7 +254,8 @@ lbf_status lbf_diagnostics(lbf_ctx* c, double* out) {
   if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
   double* part = reinterpret_cast<double*>(c->base + c->lay.off_part);
   double* dout = reinterpret_cast<double*>(c->base + c->lay.off_out);
-  HIPCHK(c, c->ops->diag(c->kp, pop_ptr(c, c->cur), aux_ptr(c, c->cur), part, dout, c->stream), "diag kernel");
+  HIPCHK(c, c->ops->diag(c->kp, kp_ptr(c), pop_ptr(c, c->cur), aux_ptr(c, c->cur), part, dout, c->stream),
+         "diag kernel");
   HIPCHK(c, hipMemcpyAsync(out, dout, (size_t)c->lay.nv * 8, hipMemcpyDeviceToHost, c->stream),
          "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");

@@ -25,7 +25,7 @@ using namespace lbf;
 
 template <class C, bool M>
 void emulate_step(StepArgs<typename C::S> a) {
-  const Geometry g = step_geometry<C>(a.P);
+  const Geometry g = step_geometry<C>(*a.P);
   a.ntx = g.ntx;
   a.nty = g.nty;
   a.chunk = g.chunk;
@@ -77,7 +77,7 @@ int run(const lbf_params* prm, const double* phi, const double* T, const double*
     a.pout = popB.data();
     a.ain = auxA.data();
     a.aout = auxB.data();
-    a.P = P;
+    a.P = &P;
     // poison the outputs: every value must be written by the step
     std::fill(popB.begin(), popB.end(), R(NAN));
     std::fill(auxB.begin(), auxB.end(), R(NAN));
@@ -99,7 +99,7 @@ int run(const lbf_params* prm, const double* phi, const double* T, const double*
       a.ain = auxA.data();
       a.mout = plane.data();
       a.mfield = k;
-      a.P = P;
+      a.P = &P;
       std::fill(plane.begin(), plane.end(), NAN);
       emulate_step<C, true>(a);
       memcpy(mom_out + (size_t)k * nc, plane.data(), (size_t)nc * 8);

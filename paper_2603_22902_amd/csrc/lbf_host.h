@@ -131,7 +131,7 @@ struct Layout {
   size_t elt;          // bytes per stored value
   size_t pop_bytes;    // one population buffer
   size_t aux_bytes;    // one lagged-field buffer
-  size_t off_pop[2], off_aux[2], off_stage, off_part, off_out, total;
+  size_t off_pop[2], off_aux[2], off_stage, off_part, off_out, off_kp, total;
   int nv;              // diagnostic values
 };
 
@@ -160,6 +160,8 @@ inline Layout make_layout(const lbf_params* P) {
   o = align256(o + (size_t)1024 * L.nv * 8);
   L.off_out = o;
   o = align256(o + (size_t)L.nv * 8);
+  L.off_kp = o;
+  o = align256(o + sizeof(KParams));
   L.total = o;
   return L;
 }

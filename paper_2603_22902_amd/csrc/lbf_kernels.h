@@ -37,8 +37,18 @@ using CfgOf = Cfg<DIM, NP, S, R, Tile<DIM, R>::TX, Tile<DIM, R>::TY>;
 // ---------------------------------------------------------------------------
 // Fused step
 // ---------------------------------------------------------------------------
+// The buffers are separate kernel parameters so that the compiler knows
+// they are global memory (global rather than flat loads and stores).
 template <class C, bool MOMENTS>
-__global__ void __launch_bounds__(C::NT) step_kernel(StepArgs<typename C::S> a) {
+__global__ void __launch_bounds__(C::NT)
+    step_kernel(const typename C::S* __restrict__ pin, typename C::S* __restrict__ pout,
+                const typename C::S* __restrict__ ain, typename C::S* __restrict__ aout,
+                double* __restrict__ mout, StepArgs<typename C::S> a) {
+  a.pin = pin;
+  a.pout = pout;
+  a.ain = ain;
+  a.aout = aout;
+  a.mout = mout;
   __shared__ Smem<C> sm;
   const BlockPos bp = block_pos<C>(a, blockIdx.x);
   const int tid = threadIdx.x;
@@ -122,7 +132,9 @@ __host__ __device__ inline void init_cell(const KParams& P, const double* fields
 }
 
 template <int DIM, int NP, typename R>
-__global__ void init_kernel(KParams P, const double* fields, int has_u, int has_p, R* pop, R* aux) {
+__global__ void init_kernel(const KParams* __restrict__ kp, const double* __restrict__ fields, int has_u,
+                            int has_p, R* __restrict__ pop, R* __restrict__ aux) {
+  const KParams& P = *kp;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell; c += stride)
     init_cell<DIM, NP, R>(P, fields, has_u, has_p, pop, aux, c);
@@ -178,8 +190,10 @@ __host__ __device__ inline void diag_cell(const KParams& P, const S* pop, const 
 constexpr int DIAG_THREADS = 256;
 
 template <int DIM, int NP, typename S, typename R>
-__global__ void __launch_bounds__(DIAG_THREADS) diag_kernel(KParams P, const S* pop, const S* aux,
-                                                            double* part) {
+__global__ void __launch_bounds__(DIAG_THREADS)
+    diag_kernel(const KParams* __restrict__ kp, const S* __restrict__ pop, const S* __restrict__ aux,
+                double* __restrict__ part) {
+  const KParams& P = *kp;
   constexpr int NV = DiagN<NP>::NV;
   __shared__ double red[NV][DIAG_THREADS];
   double acc[NV];
@@ -274,17 +288,19 @@ inline Geometry step_geometry(const KParams& P) {
 }
 
 template <int DIM, int NP, typename S, typename R>
-inline hipError_t launch_step(StepArgs<S> a, hipStream_t s, bool moments) {
+inline hipError_t launch_step(StepArgs<S> a, const KParams& hostP, hipStream_t s, bool moments) {
   using C = CfgOf<DIM, NP, S, R>;
-  const Geometry g = step_geometry<C>(a.P);
+  const Geometry g = step_geometry<C>(hostP);
   a.ntx = g.ntx;
   a.nty = g.nty;
   a.chunk = g.chunk;
   a.nblocks = g.nblocks;
   if (moments)
-    hipLaunchKernelGGL((step_kernel<C, true>), dim3(g.nblocks), dim3(g.threads), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<C, true>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin, a.pout,
+                       a.ain, a.aout, a.mout, a);
   else
-    hipLaunchKernelGGL((step_kernel<C, false>), dim3(g.nblocks), dim3(g.threads), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<C, false>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin, a.pout,
+                       a.ain, a.aout, a.mout, a);
   return hipGetLastError();
 }
 
@@ -296,20 +312,20 @@ inline int grid_for(long long n, int threads, int cap) {
 }
 
 template <int DIM, int NP, typename R>
-inline hipError_t launch_init(const KParams& P, const double* fields, int has_u, int has_p, R* pop,
-                              R* aux, hipStream_t s) {
+inline hipError_t launch_init(const KParams& P, const KParams* dP, const double* fields, int has_u,
+                              int has_p, R* pop, R* aux, hipStream_t s) {
   hipLaunchKernelGGL((init_kernel<DIM, NP, R>), dim3(grid_for(P.ncell, 256, 65536)), dim3(256), 0,
-                     s, P, fields, has_u, has_p, pop, aux);
+                     s, dP, fields, has_u, has_p, pop, aux);
   return hipGetLastError();
 }
 
 constexpr int DIAG_BLOCKS = 1024;
 
 template <int DIM, int NP, typename S, typename R>
-inline hipError_t launch_diag(const KParams& P, const S* pop, const S* aux, double* part,
-                              double* out, hipStream_t s) {
+inline hipError_t launch_diag(const KParams& P, const KParams* dP, const S* pop, const S* aux,
+                              double* part, double* out, hipStream_t s) {
   const int nb = grid_for(P.ncell, DIAG_THREADS, DIAG_BLOCKS);
-  hipLaunchKernelGGL((diag_kernel<DIM, NP, S, R>), dim3(nb), dim3(DIAG_THREADS), 0, s, P, pop, aux,
+  hipLaunchKernelGGL((diag_kernel<DIM, NP, S, R>), dim3(nb), dim3(DIAG_THREADS), 0, s, dP, pop, aux,
                      part);
   hipLaunchKernelGGL((diag_final_kernel<NP>), dim3(1), dim3(DIAG_THREADS), 0, s, part, nb,
                      1.0 / double(P.area), out);

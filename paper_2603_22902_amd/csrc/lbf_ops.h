@@ -9,13 +9,15 @@
 
 namespace lbf {
 
+// P is the host copy of the parameter block (launch geometry), dP the
+// device copy the kernels read.
 struct Ops {
   hipError_t (*step)(const void* pin, void* pout, const void* ain, void* aout, double* mout,
-                     int mfield, const KParams& P, hipStream_t s, bool moments);
-  hipError_t (*init)(const KParams& P, const double* fields, int has_u, int has_p, void* pop,
-                     void* aux, hipStream_t s);
-  hipError_t (*diag)(const KParams& P, const void* pop, const void* aux, double* part,
-                     double* out, hipStream_t s);
+                     int mfield, const KParams& P, const KParams* dP, hipStream_t s, bool moments);
+  hipError_t (*init)(const KParams& P, const KParams* dP, const double* fields, int has_u,
+                     int has_p, void* pop, void* aux, hipStream_t s);
+  hipError_t (*diag)(const KParams& P, const KParams* dP, const void* pop, const void* aux,
+                     double* part, double* out, hipStream_t s);
   hipError_t (*widen)(const void* in, double* out, long long n, hipStream_t s);
 };
 
@@ -34,8 +36,8 @@ const Ops* ops_mix(int dim, int nphase);
   template <int DIM, int NP>                                                                     \
   struct OpsImpl_##NAME {                                                                        \
     static hipError_t step(const void* pin, void* pout, const void* ain, void* aout,             \
-                           double* mout, int mfield, const KParams& P, hipStream_t s,            \
-                           bool moments) {                                                       \
+                           double* mout, int mfield, const KParams& P, const KParams* dP,        \
+                           hipStream_t s, bool moments) {                                        \
       StepArgs<ST> a;                                                                            \
       a.pin = static_cast<const ST*>(pin);                                                       \
       a.pout = static_cast<ST*>(pout);                                                           \
@@ -43,17 +45,17 @@ const Ops* ops_mix(int dim, int nphase);
       a.aout = static_cast<ST*>(aout);                                                           \
       a.mout = mout;                                                                             \
       a.mfield = mfield;                                                                         \
-      a.P = P;                                                                                   \
-      return launch_step<DIM, NP, ST, RT>(a, s, moments);                                            \
+      a.P = dP;                                                                                  \
+      return launch_step<DIM, NP, ST, RT>(a, P, s, moments);                                     \
     }                                                                                            \
-    static hipError_t init(const KParams& P, const double* fields, int has_u, int has_p,         \
-                           void* pop, void* aux, hipStream_t s) {                                \
-      return launch_init<DIM, NP, ST>(P, fields, has_u, has_p, static_cast<ST*>(pop),            \
+    static hipError_t init(const KParams& P, const KParams* dP, const double* fields, int has_u, \
+                           int has_p, void* pop, void* aux, hipStream_t s) {                     \
+      return launch_init<DIM, NP, ST>(P, dP, fields, has_u, has_p, static_cast<ST*>(pop),        \
                                       static_cast<ST*>(aux), s);                                 \
     }                                                                                            \
-    static hipError_t diag(const KParams& P, const void* pop, const void* aux, double* part,     \
-                           double* out, hipStream_t s) {                                         \
-      return launch_diag<DIM, NP, ST, RT>(P, static_cast<const ST*>(pop),                        \
+    static hipError_t diag(const KParams& P, const KParams* dP, const void* pop, const void* aux, \
+                           double* part, double* out, hipStream_t s) {                           \
+      return launch_diag<DIM, NP, ST, RT>(P, dP, static_cast<const ST*>(pop),                    \
                                           static_cast<const ST*>(aux), part, out, s);            \
     }                                                                                            \
     static hipError_t widen(const void* in, double* out, long long n, hipStream_t s) {           \

@@ -67,7 +67,7 @@ struct StepArgs {
   int ntx, nty;  // lateral tiles
   int chunk;     // layers per block
   int nblocks;
-  KParams P;
+  const KParams* P;  // device copy of the parameter block (scalar loads)
 };
 
 struct BlockPos {
@@ -79,6 +79,25 @@ __host__ __device__ inline int imod(int v, int n) {
   return r < 0 ? r + n : r;
 }
 __host__ __device__ inline int slot(int w) { return imod(w, 3); }
+// Face attributes by a run-time face index without indexing the parameter
+// block dynamically (which would force it into scratch memory).
+__host__ __device__ inline int face_flow(const KParams& P, int f) { return f == 0 ? P.flow_bc[0] : P.flow_bc[1]; }
+__host__ __device__ inline int face_therm(const KParams& P, int f) { return f == 0 ? P.therm_bc[0] : P.therm_bc[1]; }
+__host__ __device__ inline double face_T(const KParams& P, int f) { return f == 0 ? P.T_face[0] : P.T_face[1]; }
+
+// Start of plane k of a structure-of-arrays buffer (uniform across a wave,
+// so the offset stays in scalar registers and cells index it in 32 bits).
+template <typename T>
+__host__ __device__ inline T* plane(T* base, long long k, long long nc) { return base + k * nc; }
+
+// Periodic wrap of a coordinate at most one period outside [0, n).
+__host__ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// Periodic wrap of a footprint coordinate (tiles wider than the domain
+// reach further out).
+__host__ __device__ inline int wrapf(int v, int n) {
+  v = wrap1(v, n);
+  return (v < 0 || v >= n) ? imod(v, n) : v;
+}
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
 // range of logical blocks so that neighbouring tiles share an L2.
@@ -98,7 +117,7 @@ __host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, 
   bp.ty0 = (tile / a.ntx) * C::TY;
   bp.w0 = chunk_id * a.chunk;
   const int w1 = bp.w0 + a.chunk;
-  bp.w1 = w1 < a.P.nwn ? w1 : a.P.nwn;
+  bp.w1 = w1 < a.P->nwn ? w1 : a.P->nwn;
   return bp;
 }
 
@@ -149,32 +168,39 @@ __host__ __device__ inline float gprime(float x) { return 2.0f * x * (1.0f - x) 
 // ---------------------------------------------------------------------------
 // Fill: moments of one footprint cell of a real layer into the LDS ring.
 // phi_p = sum_i g_{i,p} / (1 - D^{n-1}/2); rho H = sum_i h_i + q^{n-1}/2.
+// Cell indices are 32-bit (the host limits a grid to 2^30 cells); plane
+// offsets k * ncell are formed in 64-bit once per plane.
 // ---------------------------------------------------------------------------
 template <class C>
 __host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
                                           const BlockPos& bp, int f, int w) {
   using R = typename C::R;
+  using ST = typename C::S;
   constexpr int Q = C::Q, NP = C::NP;
-  const KParams& P = a.P;
+  const KParams& P = *a.P;
   const int lx = f % C::LX, ly = f / C::LX;
-  long long lat = imod(bp.tx0 + lx - 1, P.nx);
-  if (C::DIM == 3) lat += (long long)imod(bp.ty0 + ly - 1, P.ny) * P.nx;
-  const long long nc = P.ncell, cell = (long long)w * P.area + lat;
-  const R div = R(a.ain[C::A_DIV * nc + cell]);
-  const R qv = R(a.ain[C::A_Q * nc + cell]);
+  int lat = wrapf(bp.tx0 + lx - 1, P.nx);
+  if (C::DIM == 3) lat += wrapf(bp.ty0 + ly - 1, P.ny) * P.nx;
+  const long long nc = P.ncell;
+  const int cell = w * (int)P.area + lat;
+  const ST* __restrict__ pin = a.pin;
+  const ST* __restrict__ ain = a.ain;
+  const R div = R(plane(ain, C::A_DIV, nc)[cell]);
+  const R qv = R(plane(ain, C::A_Q, nc)[cell]);
   const int s = slot(w);
+  const R idiv = R(1) / (R(1) - R(0.5) * div);
   R phi[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     R sum = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sum += R(a.pin[((1 + p) * Q + i) * nc + cell]);
-    phi[p] = sum / (R(1) - R(0.5) * div);
+    for (int i = 0; i < Q; ++i) sum += R(plane(pin, (1 + p) * Q + i, nc)[cell]);
+    phi[p] = sum * idiv;
     sm.phi[s][p][f] = phi[p];
   }
   double sh = 0.0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) sh += double(a.pin[((NP + 1) * Q + i) * nc + cell]);
+  for (int i = 0; i < Q; ++i) sh += double(plane(pin, (NP + 1) * Q + i, nc)[cell]);
   const double rhoH = sh + 0.5 * double(qv);
   double T, fl;
   invert<NP>(P, phi, rhoH, T, fl);
@@ -182,7 +208,7 @@ __host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem
   sm.fs[s][f] = fs;
   sm.rho[s][f] = mixture<R, NP>(phi, fs, P.rho_s, P.rho_l);
 #pragma unroll
-  for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = R(a.ain[(C::A_U + d) * nc + cell]);
+  for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = R(plane(ain, C::A_U + d, nc)[cell]);
   sm.rhoH[s][f] = rhoH;
   sm.T[s][f] = T;
 }
@@ -198,7 +224,7 @@ __host__ __device__ inline void fill_ghost(const StepArgs<typename C::S>& a, Sme
                                            int w) {
   using R = typename C::R;
   constexpr int NP = C::NP;
-  const KParams& P = a.P;
+  const KParams& P = *a.P;
   const int face = (w < 0) ? 0 : 1;
   const int sb = slot(face == 0 ? 0 : P.nwn - 1), s = slot(w);
   if (face == 0 && P.flow_bc[0] == BC_WALL) {
@@ -219,7 +245,7 @@ __host__ __device__ inline void fill_ghost(const StepArgs<typename C::S>& a, Sme
   }
   sm.fs[s][f] = sm.fs[sb][f];
   sm.rho[s][f] = sm.rho[sb][f];
-  const R sgn = (P.flow_bc[face] == BC_WALL) ? R(-1) : R(1);
+  const R sgn = (face_flow(P, face) == BC_WALL) ? R(-1) : R(1);
 #pragma unroll
   for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = sgn * sm.u[sb][d][f];
   sm.rhoH[s][f] = sm.rhoH[sb][f];
@@ -229,18 +255,18 @@ __host__ __device__ inline void fill_ghost(const StepArgs<typename C::S>& a, Sme
 template <class C>
 __host__ __device__ inline void fill_layer_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
                                                 const BlockPos& bp, int f, int w) {
-  if (w < 0 || w >= a.P.nwn)
+  if (w < 0 || w >= a.P->nwn)
     fill_ghost<C>(a, sm, f, w);
   else
     fill_cell<C>(a, sm, bp, f, w);
 }
 
 // Push of one post-collision population: x + c_i inside the domain gets it;
-// a link leaving through a wall-normal face instead stores the face's value
-// for the opposite (incoming) direction at this cell.
+// a link leaving through a wall-normal face (face = 0 or 1, return -1)
+// instead stores the face's value for the opposite, incoming direction at
+// this cell.
 template <class C>
-__host__ __device__ inline long long push_index(const KParams& P, int i, int gx, int gy, int w,
-                                                int& face) {
+__host__ __device__ inline int push_index(const KParams& P, int i, int gx, int gy, int w, int& face) {
   using L = typename C::L;
   const int tw = w + L::cw(i);
   if (tw < 0 || tw >= P.nwn) {
@@ -248,9 +274,23 @@ __host__ __device__ inline long long push_index(const KParams& P, int i, int gx,
     return -1;
   }
   face = -1;
-  long long lat = imod(gx + L::cl0(i), P.nx);
-  if (C::DIM == 3) lat += (long long)imod(gy + L::cl1(i), P.ny) * P.nx;
-  return (long long)tw * P.area + lat;
+  int lat = wrap1(gx + L::cl0(i), P.nx);
+  if (C::DIM == 3) lat += wrap1(gy + L::cl1(i), P.ny) * P.nx;
+  return tw * (int)P.area + lat;
+}
+
+// c_i . v for direction i of the lattice (components +-1 or 0 folded at
+// compile time once the direction loops are unrolled).
+template <class C, typename R>
+__host__ __device__ inline R cdot(int i, const R* v) {
+  using L = typename C::L;
+  R s = R(0);
+#pragma unroll
+  for (int d = 0; d < C::DIM; ++d) {
+    if (L::c(i, d) > 0) s += v[d];
+    if (L::c(i, d) < 0) s -= v[d];
+  }
+  return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -265,16 +305,19 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   using ST = typename C::S;  // storage type
   using L = typename C::L;
   constexpr int Q = C::Q, NP = C::NP, DIM = C::DIM;
-  const KParams& P = a.P;
+  const KParams& P = *a.P;
   const int tx = tid % C::TX, ty = tid / C::TX;
   const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
   if (gx >= P.nx) return;
   if (DIM == 3 && gy >= P.ny) return;
   const long long nc = P.ncell;
-  const long long lat = (DIM == 3) ? (long long)gy * P.nx + gx : (long long)gx;
-  const long long cell = (long long)w * P.area + lat;
+  const int lat = (DIM == 3) ? gy * P.nx + gx : gx;
+  const int cell = w * (int)P.area + lat;
   const int fc = (DIM == 3) ? (ty + 1) * C::LX + tx + 1 : tx + 1;
   const int s0 = slot(w);
+  const ST* __restrict__ pin = a.pin;
+  const ST* __restrict__ ain = a.ain;
+  ST* __restrict__ pout = a.pout;
 
   // Own moments (identical to the values the neighbours see).
   R phi[NP];
@@ -289,9 +332,6 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
 #pragma unroll
   for (int p = 0; p < NP; ++p)
     if (P.freezes[p]) psi += phi[p];
-  const R mu = mixture<R, NP>(phi, fs, P.mu_s, P.mu_l);
-  const R lam = mixture<R, NP>(phi, fs, P.lam_s, P.lam_l);
-  const R cp = mixture<R, NP>(phi, fs, P.cp_s, P.cp_l);
   R uprev[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) uprev[d] = sm.u[s0][d][fc];
@@ -317,20 +357,19 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
     for (int p = 0; p < NP; ++p) {
       const R X = sm.phi[sn][p][fn];
       const R t = wi * X;
+      const R tf = wi * (fsn * X);
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        if (L::c(i, d) > 0) gphi[p][d] += t;
-        if (L::c(i, d) < 0) gphi[p][d] -= t;
-      }
-      lphi[p] += wi * (X - phi[p]);
-      if (P.freezes[p]) {
-        const R tf = wi * (fsn * X);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          if (L::c(i, d) > 0) gfp[p][d] += tf;
-          if (L::c(i, d) < 0) gfp[p][d] -= tf;
+        if (L::c(i, d) > 0) {
+          gphi[p][d] += t;
+          gfp[p][d] += tf;
+        }
+        if (L::c(i, d) < 0) {
+          gphi[p][d] -= t;
+          gfp[p][d] -= tf;
         }
       }
+      lphi[p] += wi * (X - phi[p]);
     }
     const R tr = wi * sm.rho[sn][fn];
 #pragma unroll
@@ -363,8 +402,14 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   }
 
   // Step 4: interface physics of Sec. 2.  Pairwise normals via the quotient
-  // rule, v = phi_q grad phi_p - phi_p grad phi_q, |v| regularised by 1e-12.
-  R nrm[NP][NP][DIM];
+  // rule, v = phi_q grad phi_p - phi_p grad phi_q, |v| regularised by 1e-12;
+  // each pair adds 4 phi_p phi_q / eps n_pq to R_p and its negative to R_q.
+  R Rp[NP][DIM], mup[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Rp[p][d] = R(0);
+  const R ieps = R(1) / R(P.eps);
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -375,30 +420,21 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
         v[d] = phi[q] * gphi[p][d] - phi[p] * gphi[q][d];
         vv += v[d] * v[d];
       }
-      const R inv = R(1) / sqrt(vv + R(1e-24));
+      const R sc = R(4) * phi[p] * phi[q] * ieps / sqrt(vv + R(1e-24));
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        nrm[p][q][d] = v[d] * inv;
-        nrm[q][p][d] = -nrm[p][q][d];
+        Rp[p][d] += sc * v[d];
+        Rp[q][d] -= sc * v[d];
       }
     }
-  R Rp[NP][DIM], mup[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) Rp[p][d] = R(0);
     R bulk = R(0), gterm = R(0);
+    const R gp = gprime(phi[p]);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       if (q == p) continue;
-      const R sc = R(4) * phi[p] * phi[q] / R(P.eps);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) Rp[p][d] += sc * nrm[p][q][d];
-      bulk += R(2) * R(P.beta[p][q]) * (gprime(phi[p]) - gprime(phi[p] + phi[q]));
-    }
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      if (q == p) continue;
+      bulk += R(2) * R(P.beta[p][q]) * (gp - gprime(phi[p] + phi[q]));
       gterm += R(P.kpq[p][q]) * lphi[q];
     }
     mup[p] = bulk - gterm;
@@ -415,39 +451,42 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   // Step 5: flow macros.
   R fpop[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) fpop[i] = R(a.pin[i * nc + cell]);
+  for (int i = 0; i < Q; ++i) fpop[i] = R(plane(pin, i, nc)[cell]);
   R mom[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) mom[d] = R(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
+  for (int i = 1; i < Q; ++i)
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       if (L::c(i, d) > 0) mom[d] += fpop[i];
       if (L::c(i, d) < 0) mom[d] -= fpop[i];
     }
+  const R irho = R(1) / rho;
   const R ws = fs * psi;
-  R u[DIM], rhoa[DIM];
+  R u[DIM], Fa[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const R us = (mom[d] + R(0.5) * F[d]) / rho;
+    const R us = (mom[d] + R(0.5) * F[d]) * irho;
     const R acc = ws * (R(0) - us);
     u[d] = us + R(0.5) * acc;
-    rhoa[d] = rho * acc;
+    Fa[d] = F[d] + rho * acc;  // F + rho a
   }
   // mdot = -(1/rho) sum_{p freezing} (rho_p^s - rho_p^l) D(f_s phi_p)/Dt
   R msum = R(0);
+  const R fsp = R(plane(ain, C::A_FS, nc)[cell]);
+  R phip[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) phip[p] = R(plane(ain, p, nc)[cell]);
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     if (!P.freezes[p]) continue;
-    const R phip = R(a.ain[p * nc + cell]);
-    const R fsp = R(a.ain[C::A_FS * nc + cell]);
     R ug = R(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) ug += u[d] * gfp[p][d];
-    msum += R(P.rho_s[p] - P.rho_l[p]) * (fs * phi[p] - fsp * phip + ug);
+    msum += R(P.rho_s[p] - P.rho_l[p]) * (fs * phi[p] - fsp * phip[p] + ug);
   }
-  const R mdot = -msum / rho;
+  const R mdot = -msum * irho;
   R ugr = R(0), uu = R(0);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -456,38 +495,24 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   }
   const R S = rho * mdot + ugr;
   // Forcing F_i = w_i [S + 3 c.(F + rho a) + 9/2 (c c - I/3) : Lambda],
-  // Lambda = u F + F u + (2/d) rho cs2 S I.
-  R Lam[DIM][DIM];
+  // Lambda = u F + F u + (2/d) rho cs2 S I; (c c - I/3):Lambda =
+  // 2 (c.u)(c.F) + (2/d) rho cs2 S (|c|^2 - d/3) - 2/3 u.F.
+  R uF = R(0);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d)
-#pragma unroll
-    for (int e = 0; e < DIM; ++e)
-      Lam[d][e] = u[d] * F[e] + F[d] * u[e] +
-                  (d == e ? R(2.0 / DIM) * rho * R(1.0 / 3.0) * S : R(0));
-  R Fi[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    R cF = R(0);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (L::c(i, d) > 0) cF += F[d] + rhoa[d];
-      if (L::c(i, d) < 0) cF -= F[d] + rhoa[d];
-    }
-    R qq = R(0);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d)
-#pragma unroll
-      for (int e = 0; e < DIM; ++e)
-        qq += (R(L::c(i, d) * L::c(i, e)) - (d == e ? R(1.0 / 3.0) : R(0))) * Lam[d][e];
-    Fi[i] = wgt<R, DIM>(i) * (S + R(3) * cF + R(4.5) * qq);
-  }
-  const R tau_f = R(3) * mu / rho + R(0.5);
+  for (int d = 0; d < DIM; ++d) uF += u[d] * F[d];
+  const R lam_iso = R(2.0 / DIM) * rho * R(1.0 / 3.0) * S;
+  const R mu = mixture<R, NP>(phi, fs, P.mu_s, P.mu_l);
+  const R tau_f = R(3) * mu * irho + R(0.5);
+  const R itf = R(1) / tau_f;
+  const R sfac = R(1) - R(0.5) * itf;
+  const R w0 = wgt<R, DIM>(0);
   R sf = R(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) sf += fpop[i];
-  const R w0 = wgt<R, DIM>(0);
-  const R s0u = w0 * (R(0) + R(0) - R(1.5) * uu);
-  const R pr = R(1.0 / 3.0) / (R(1) - w0) * (sf + R(0.5) * S + (tau_f - R(0.5)) * Fi[0] + rho * s0u);
+  // F_0 (c_0 = 0): w_0 [S + 9/2 (-1/3) tr Lambda]
+  const R F0 = w0 * (S + R(4.5) * (-R(2.0 / 3.0) * uF - R(DIM) * R(1.0 / 3.0) * lam_iso));
+  const R s0u = w0 * (-R(1.5) * uu);
+  const R pr = R(1.0 / 3.0) / (R(1) - w0) * (sf + R(0.5) * S + (tau_f - R(0.5)) * F0 + rho * s0u);
 
   if (MOMENTS) {
     const int k = a.mfield;
@@ -509,100 +534,74 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
 
   // Step 6-7: collisions and push streaming.
   // Flow LB: f^eq_0 = 3p (w_0 - 1) + rho s_0, f^eq_i = 3p w_i + rho s_i.
-  const R itf = R(1) / tau_f;
-  const R sfac = R(1) - R(0.5) / tau_f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    R cu = R(0);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (L::c(i, d) > 0) cu += u[d];
-      if (L::c(i, d) < 0) cu -= u[d];
-    }
+    const R cu = cdot<C>(i, u);
+    const R cF = cdot<C>(i, Fa);
+    const R cFs = cdot<C>(i, F);
     const R wi = wgt<R, DIM>(i);
+    const R c2 = R(L::c(i, 0) * L::c(i, 0) + L::c(i, 1) * L::c(i, 1) + L::c(i, 2) * L::c(i, 2));
+    const R qq = R(2) * cu * cFs - R(2.0 / 3.0) * uF + lam_iso * (c2 - R(DIM) * R(1.0 / 3.0));
+    const R Fi = wi * (S + R(3) * cF + R(4.5) * qq);
     const R si = wi * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
     const R fe = (i == 0) ? R(3) * pr * (w0 - R(1)) + rho * si : R(3) * pr * wi + rho * si;
-    const R post = fpop[i] - (fpop[i] - fe) / tau_f + sfac * Fi[i];
+    const R post = fpop[i] - (fpop[i] - fe) * itf + sfac * Fi;
     int face;
-    const long long t = push_index<C>(P, i, gx, gy, w, face);
+    const int t = push_index<C>(P, i, gx, gy, w, face);
     if (t >= 0) {
-      a.pout[i * nc + t] = ST(post);
+      plane(pout, i, nc)[t] = ST(post);
     } else {
       const int ib = L::opp(i);
       R val;
-      if (P.flow_bc[face] == BC_WALL) {
+      if (face_flow(P, face) == BC_WALL) {
         val = post;  // halfway bounce-back
       } else {
         // open face: ghost at pressure 0 with this cell's u and rho
-        R cub = R(0);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          if (L::c(ib, d) > 0) cub += u[d];
-          if (L::c(ib, d) < 0) cub -= u[d];
-        }
+        const R cub = -cu;
         const R wb = wgt<R, DIM>(ib);
         const R sb = wb * (R(3) * cub + R(4.5) * cub * cub - R(1.5) * uu);
         const R feb = R(3) * pr * wb + rho * sb;
         val = rho * sb + (R(1) - itf) * (fpop[ib] - feb);
       }
-      a.pout[ib * nc + cell] = ST(val);
+      plane(pout, ib, nc)[cell] = ST(val);
     }
   }
 
   // Phase-field LBs: g^eq = w_i phi (1 + 3 c.u),
   // G = w_i [3 c.(phi u - phi^{n-1} u^{n-1}) + c.R_p] + w_i phi D.
-  const R tg = R(P.tau_g);
-  const R gfac = R(1) - R(0.5) / tg;
+  const R itg = R(1) / R(P.tau_g);
+  const R gfac = R(1) - R(0.5) * itg;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    const R phip = R(a.ain[p * nc + cell]);
     R dpu[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) dpu[d] = phi[p] * u[d] - phip * uprev[d];
+    for (int d = 0; d < DIM; ++d) dpu[d] = R(3) * (phi[p] * u[d] - phip[p] * uprev[d]) + Rp[p][d];
+    const int l = 1 + p;
     R gpop[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) gpop[i] = R(a.pin[((1 + p) * Q + i) * nc + cell]);
+    for (int i = 0; i < Q; ++i) gpop[i] = R(plane(pin, l * Q + i, nc)[cell]);
+    const R phD = phi[p] * Ddiv;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      R cd = R(0), cr = R(0), cu = R(0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        if (L::c(i, d) > 0) {
-          cd += dpu[d];
-          cr += Rp[p][d];
-          cu += u[d];
-        }
-        if (L::c(i, d) < 0) {
-          cd -= dpu[d];
-          cr -= Rp[p][d];
-          cu -= u[d];
-        }
-      }
+      const R cu = cdot<C>(i, u);
       const R wi = wgt<R, DIM>(i);
-      const R Gi = wi * (R(3) * cd + cr) + wi * phi[p] * Ddiv;
+      const R Gi = wi * (cdot<C>(i, dpu) + phD);
       const R ge = wi * phi[p] * (R(1) + R(3) * cu);
-      const R post = gpop[i] - (gpop[i] - ge) / tg + gfac * Gi;
+      const R post = gpop[i] - (gpop[i] - ge) * itg + gfac * Gi;
       int face;
-      const long long t = push_index<C>(P, i, gx, gy, w, face);
-      const int l = 1 + p;
+      const int t = push_index<C>(P, i, gx, gy, w, face);
       if (t >= 0) {
-        a.pout[(l * Q + i) * nc + t] = ST(post);
+        plane(pout, l * Q + i, nc)[t] = ST(post);
       } else {
         const int ib = L::opp(i);
         R val;
-        if (P.flow_bc[face] == BC_WALL) {
+        if (face_flow(P, face) == BC_WALL) {
           val = post;
         } else {
-          R cub = R(0);
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            if (L::c(ib, d) > 0) cub += u[d];
-            if (L::c(ib, d) < 0) cub -= u[d];
-          }
-          const R geb = wgt<R, DIM>(ib) * phi[p] * (R(1) + R(3) * cub);
-          val = geb + (R(1) - R(1) / tg) * (gpop[ib] - geb);
+          const R geb = wgt<R, DIM>(ib) * phi[p] * (R(1) - R(3) * cu);
+          val = geb + (R(1) - itg) * (gpop[ib] - geb);
         }
-        a.pout[(l * Q + ib) * nc + cell] = ST(val);
+        plane(pout, l * Q + ib, nc)[cell] = ST(val);
       }
     }
   }
@@ -611,83 +610,70 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   // h^eq_i = w_i [E_ref T + rho C_p T (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)],
   // H_i = w_i rho C_p T D, tau_h = 3 lambda / E_ref + 1/2.  The rest
   // population is updated in float64 (it carries the latent heat offset).
+  const R lam = mixture<R, NP>(phi, fs, P.lam_s, P.lam_l);
+  const R cp = mixture<R, NP>(phi, fs, P.cp_s, P.cp_l);
   const R rhocp = rho * cp;
   const R Eref = R(P.E_ref);
   const R tau_h = R(3) * lam / Eref + R(0.5);
-  const R hfac = R(1) - R(0.5) / tau_h;
+  const R ith = R(1) / tau_h;
+  const R hfac = R(1) - R(0.5) * ith;
+  const R ET = Eref * T, CT = rhocp * T, HD = CT * Ddiv;
+  const int lh = NP + 1;
   R hpop[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) hpop[i] = R(a.pin[((NP + 1) * Q + i) * nc + cell]);
+  for (int i = 0; i < Q; ++i) hpop[i] = R(plane(pin, lh * Q + i, nc)[cell]);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const R wi = wgt<R, DIM>(i);
+    const R cu = cdot<C>(i, u);
     R post;
-    R he;
     if (i == 0) {
       const double Er = P.E_ref;
       const double rc = double(rhocp);
-      const double he0 =
-          rhoH - Er * Td + double(w0) * (Er * Td - 1.5 * rc * Td * double(uu));
+      const double he0 = rhoH - Er * Td + double(w0) * (Er * Td - 1.5 * rc * Td * double(uu));
       const double H0 = double(wi) * rc * Td * double(Ddiv);
-      const double td = double(tau_h);
+      const double ithd = double(ith);
       const double h0 = double(hpop[0]);
-      post = R(h0 - (h0 - he0) / td + (1.0 - 0.5 / td) * H0);
-      he = R(he0);
+      post = R(h0 - (h0 - he0) * ithd + (1.0 - 0.5 * ithd) * H0);
     } else {
-      R cu = R(0);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        if (L::c(i, d) > 0) cu += u[d];
-        if (L::c(i, d) < 0) cu -= u[d];
-      }
-      he = wi * (Eref * T + rhocp * T * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-      const R Hi = wi * rhocp * T * Ddiv;
-      post = hpop[i] - (hpop[i] - he) / tau_h + hfac * Hi;
+      const R he = wi * (ET + CT * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+      post = hpop[i] - (hpop[i] - he) * ith + hfac * (wi * HD);
     }
     int face;
-    const long long t = push_index<C>(P, i, gx, gy, w, face);
+    const int t = push_index<C>(P, i, gx, gy, w, face);
     if (t >= 0) {
-      a.pout[((NP + 1) * Q + i) * nc + t] = ST(post);
+      plane(pout, lh * Q + i, nc)[t] = ST(post);
     } else {
       const int ib = L::opp(i);
       R val;
-      if (P.flow_bc[face] == BC_WALL && P.therm_bc[face] == TBC_ADIABATIC) {
+      if (face_flow(P, face) == BC_WALL && face_therm(P, face) == TBC_ADIABATIC) {
         val = post;
       } else {
-        const R Tg = (P.therm_bc[face] == TBC_DIRICHLET) ? R(2) * R(P.T_face[face]) - T : T;
-        R ug[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) ug[d] = (P.flow_bc[face] == BC_OPEN) ? u[d] : R(0);
-        R cub = R(0), cuc = R(0), ugug = R(0);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          if (L::c(ib, d) > 0) {
-            cub += ug[d];
-            cuc += u[d];
-          }
-          if (L::c(ib, d) < 0) {
-            cub -= ug[d];
-            cuc -= u[d];
-          }
-          ugug += ug[d] * ug[d];
-        }
+        // Ghost node half a cell outside the face at T_g (Dirichlet:
+        // 2 T_face - T), velocity 0 at walls and u at open faces; this
+        // cell's non-equilibrium part.
+        const R Tg = (face_therm(P, face) == TBC_DIRICHLET) ? R(2) * R(face_T(P, face)) - T : T;
+        const bool open = face_flow(P, face) == BC_OPEN;
+        const R cub = open ? -cu : R(0);
+        const R ugug = open ? uu : R(0);
         const R wb = wgt<R, DIM>(ib);
         const R hg = wb * (Eref * Tg + rhocp * Tg * (R(3) * cub + R(4.5) * cub * cub - R(1.5) * ugug));
-        const R heb = wb * (Eref * T + rhocp * T * (R(3) * cuc + R(4.5) * cuc * cuc - R(1.5) * uu));
-        val = hg + (R(1) - R(1) / tau_h) * (hpop[ib] - heb);
+        const R heb = wb * (ET + CT * (-R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+        val = hg + (R(1) - ith) * (hpop[ib] - heb);
       }
-      a.pout[((NP + 1) * Q + ib) * nc + cell] = ST(val);
+      plane(pout, lh * Q + ib, nc)[cell] = ST(val);
     }
   }
 
   // Lagged fields for the next step.
+  ST* __restrict__ aout = a.aout;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) a.aout[p * nc + cell] = ST(phi[p]);
-  a.aout[C::A_FS * nc + cell] = ST(fs);
+  for (int p = 0; p < NP; ++p) plane(aout, p, nc)[cell] = ST(phi[p]);
+  plane(aout, C::A_FS, nc)[cell] = ST(fs);
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) a.aout[(C::A_U + d) * nc + cell] = ST(u[d]);
-  a.aout[C::A_DIV * nc + cell] = ST(Ddiv);
-  a.aout[C::A_Q * nc + cell] = ST(rhocp * T * Ddiv);
+  for (int d = 0; d < DIM; ++d) plane(aout, C::A_U + d, nc)[cell] = ST(u[d]);
+  plane(aout, C::A_DIV, nc)[cell] = ST(Ddiv);
+  plane(aout, C::A_Q, nc)[cell] = ST(HD);
 }
 
 }  // namespace lbf
