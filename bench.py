@@ -1,4 +1,4 @@
-"""Throughput of the fused coupled-LB step on one MI355X.
+"""Throughput of the coupled-LB time step on one MI355X.
 
 One "step" is one time step of the whole coupled method (three LBs,
 moments, enthalpy inversion, finite differences, interface physics,
@@ -9,9 +9,11 @@ memory, uploaded, and resident in HBM before timing starts.
 
 Prints one JSON line with MLUPS (million lattice updates per second, with
 conservation diagnostics every 100 steps inside the timed region), the
-HBM roofline of the step kernel (algorithmic bytes per launch over its
-average launch time, measured with HIP events on the solver's stream),
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+HBM roofline of the dominant kernel, the collide pass (its algorithmic
+bytes per launch over its average launch time, measured with HIP events
+on the solver's stream around each launch), the same for the moments pass
+and for the whole step, and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--workload impurities|droplet|compound|film]
                   [--precision fp32|mixed|fp64] [--no-cpu-baseline]
@@ -41,10 +43,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes_per_cell(dim: int, N: int, elt: int) -> int:
-    """Each population and lagged field read once and written once."""
+def algorithmic_bytes_per_cell(dim: int, N: int, elt: int) -> dict:
+    """Bytes per cell that each pass must move at least, and the step's
+    state (every population and lagged field read once and written once).
+
+    moments: reads g, h ((N+1) Q), D, q; writes phi_p, f_s (N+1).
+    collide: reads f, g, h ((N+2) Q), phi_p and f_s at n and n-1 (2(N+1)),
+             u^{n-1} (dim), q^{n-1}; writes f, g, h, u (dim), D, q.
+    """
     Q = 9 if dim == 2 else 19
-    return 2 * elt * ((N + 2) * Q + (N + dim + 3))
+    return {"moments": elt * ((N + 1) * Q + 2 + (N + 1)),
+            "collide": elt * (2 * (N + 2) * Q + 2 * (N + 1) + 2 * dim + 3),
+            "step": 2 * elt * ((N + 2) * Q + (N + dim + 3))}
 
 
 def measured_traffic(workload: str, precision: str):
@@ -110,8 +120,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this solver's hot path is one kernel on one "
-              "device; multi-GPU slab decomposition is not part of this build.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver's time step runs on one device; "
+              "a multi-GPU slab decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -147,21 +157,16 @@ def main():
     print(f"[bench] timed {args.steps} steps: {ms_total:.2f} ms (host wall {wall * 1e3:.2f} ms)",
           file=sys.stderr, flush=True)
 
-    # Timed region 2 (roofline): back-to-back step launches only.
+    # Timed region 2 (roofline): HIP events around each launch of K steps.
     k_steps = max(20, args.steps // 2)
-    start.record(stream)
-    s.lbf_step(k_steps)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms_kernel = start.elapsed_time(stop) / k_steps
+    ms_mom, ms_col = s.lbf_step_timed(k_steps)
     diag = s.lbf_diagnostics(check_nan=False)
-    print(f"[bench] step kernel {ms_kernel * 1e3:.1f} us/launch; front {diag['front']:.4f} "
-          f"nonfinite {diag['nonfinite']}", file=sys.stderr, flush=True)
+    print(f"[bench] moments {ms_mom * 1e3:.1f} us, collide {ms_col * 1e3:.1f} us per launch; "
+          f"front {diag['front']:.4f} nonfinite {diag['nonfinite']}", file=sys.stderr, flush=True)
 
     elt = 8 if args.precision == "fp64" else 4
     bpc = algorithmic_bytes_per_cell(prm["dim"], prm["nphase"], elt)
-    bytes_per_launch = bpc * ncell
-    achieved = bytes_per_launch / (ms_kernel * 1e-3) / 1e9
+    achieved = bpc["collide"] * ncell / (ms_col * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, args.precision)
     ms_per_step = ms_total / args.steps
     mlups = ncell * args.steps / (ms_total * 1e-3) / 1e6
@@ -173,8 +178,16 @@ def main():
         "data": "synthetic", "config": describe(case),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "step_kernel", "kernel_us": round(ms_kernel * 1e3, 2),
-                     "bytes_per_cell": bpc, "mlups_kernel_only": round(ncell / (ms_kernel * 1e-3) / 1e6, 2)},
+                     "kernel": "collide_kernel", "kernel_us": round(ms_col * 1e3, 2),
+                     "bytes_per_cell": bpc["collide"]},
+        "kernels": {
+            "moment_kernel": {"us": round(ms_mom * 1e3, 2), "bytes_per_cell": bpc["moments"],
+                              "GB/s": round(bpc["moments"] * ncell / (ms_mom * 1e-3) / 1e9, 1)},
+            "collide_kernel": {"us": round(ms_col * 1e3, 2), "bytes_per_cell": bpc["collide"],
+                               "GB/s": round(achieved, 1)},
+            "step": {"us": round((ms_mom + ms_col) * 1e3, 2), "state_bytes_per_cell": bpc["step"],
+                     "GB/s": round(bpc["step"] * ncell / ((ms_mom + ms_col) * 1e-3) / 1e9, 1),
+                     "mlups_kernels_only": round(ncell / ((ms_mom + ms_col) * 1e-3) / 1e6, 2)}},
     }
     if not args.no_cpu_baseline:
         del s

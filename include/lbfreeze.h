@@ -128,8 +128,19 @@ lbf_status lbf_create(const lbf_params* prm, void* dev_buf, size_t bytes, void* 
 lbf_status lbf_init_fields(lbf_ctx* ctx, const double* phi, const double* T, const double* u,
                            const double* p);
 
-/* Advance nsteps >= 0 time steps (one fused kernel launch per step). */
+/* Advance nsteps >= 0 time steps, Sec. 3.  Each step is two kernel launches
+ * on the context's stream: a moments pass (phi_p, f_s of every cell from its
+ * populations) and a collide pass (finite differences, interface and flow
+ * sources, the three collisions, push streaming and boundary rules). */
 lbf_status lbf_step(lbf_ctx* ctx, int nsteps);
+
+/* lbf_step with per-kernel timing: the same launches, bracketed by HIP events
+ * on the context's stream.  On return (the stream has been synchronised)
+ * ms[0] and ms[1] hold the average duration per step, in milliseconds, of
+ * the moments and the collide launch.  1 <= nsteps <= 4096 (LBF_EINVAL
+ * otherwise); ms must point to 2 doubles.  The state advances exactly as
+ * with lbf_step. */
+lbf_status lbf_step_timed(lbf_ctx* ctx, int nsteps, double* ms);
 
 /* Macroscopic fields at the current time level (moments of the current
  * populations, inversion, and the flow macros u, p, mdot of Sec. 3), for the

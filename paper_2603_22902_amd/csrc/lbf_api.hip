@@ -195,11 +195,74 @@ lbf_status lbf_step(lbf_ctx* c, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     const int a = c->cur, b = 1 - c->cur;
     HIPCHK(c, c->ops->step(pop_ptr(c, a), pop_ptr(c, b), aux_ptr(c, a), aux_ptr(c, b), nullptr, 0, c->kp,
-                           kp_ptr(c), c->stream, false),
-           "step kernel");
+                           kp_ptr(c), c->stream, false, 3),
+           "step kernels");
     c->cur = b;
     ++c->steps;
   }
+  return LBF_OK;
+}
+
+lbf_status lbf_step_timed(lbf_ctx* c, int nsteps, double* ms) {
+  if (!c) return LBF_EINVAL;
+  if (!ms) return fail(c, LBF_EINVAL, "ms is NULL");
+  if (nsteps < 1 || nsteps > 4096) return fail(c, LBF_EINVAL, "nsteps must be in [1, 4096]");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  const int ne = 2 * nsteps + 1;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[ne];
+  if (!ev) return fail(c, LBF_ENOMEM, "event table");
+  int made = 0;
+  hipError_t e = hipSuccess;
+  for (; made < ne && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+  if (e != hipSuccess) --made;
+  const char* what = "hipEventCreate";
+  int done = 0;
+  if (e == hipSuccess) {
+    what = "hipEventRecord";
+    e = hipEventRecord(ev[0], c->stream);
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+      const int a = c->cur, b = 1 - c->cur;
+      what = "moments kernel";
+      e = c->ops->step(pop_ptr(c, a), pop_ptr(c, b), aux_ptr(c, a), aux_ptr(c, b), nullptr, 0, c->kp,
+                       kp_ptr(c), c->stream, false, 1);
+      if (e == hipSuccess) {
+        what = "hipEventRecord";
+        e = hipEventRecord(ev[2 * s + 1], c->stream);
+      }
+      if (e == hipSuccess) {
+        what = "collide kernel";
+        e = c->ops->step(pop_ptr(c, a), pop_ptr(c, b), aux_ptr(c, a), aux_ptr(c, b), nullptr, 0, c->kp,
+                         kp_ptr(c), c->stream, false, 2);
+      }
+      if (e == hipSuccess) {
+        what = "hipEventRecord";
+        e = hipEventRecord(ev[2 * s + 2], c->stream);
+      }
+      if (e == hipSuccess) {
+        c->cur = b;
+        ++c->steps;
+        ++done;
+      }
+    }
+  }
+  if (e == hipSuccess) {
+    what = "hipEventSynchronize";
+    e = hipEventSynchronize(ev[ne - 1]);
+  }
+  double tm = 0.0, tc = 0.0;
+  for (int s = 0; s < done && e == hipSuccess; ++s) {
+    float t1 = 0.f, t2 = 0.f;
+    what = "hipEventElapsedTime";
+    e = hipEventElapsedTime(&t1, ev[2 * s], ev[2 * s + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t2, ev[2 * s + 1], ev[2 * s + 2]);
+    tm += t1;
+    tc += t2;
+  }
+  for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+  delete[] ev;
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  ms[0] = tm / nsteps;
+  ms[1] = tc / nsteps;
   return LBF_OK;
 }
 
@@ -222,9 +285,11 @@ lbf_status lbf_get_moments(lbf_ctx* c, unsigned mask, double* out) {
   if (mask & LBF_M_P) ids[nf++] = N + 4 + d;
   if (mask & LBF_M_MDOT) ids[nf++] = N + 5 + d;
   const int a = c->cur;
+  // The other aux buffer is free between steps: the moments pass writes
+  // phi_p, f_s there.
   for (int k = 0; k < nf; ++k) {
-    HIPCHK(c, c->ops->step(pop_ptr(c, a), nullptr, aux_ptr(c, a), nullptr, stage_ptr(c), ids[k], c->kp,
-                           kp_ptr(c), c->stream, true),
+    HIPCHK(c, c->ops->step(pop_ptr(c, a), nullptr, aux_ptr(c, a), aux_ptr(c, 1 - a), stage_ptr(c), ids[k], c->kp,
+                           kp_ptr(c), c->stream, true, 3),
            "moments kernel");
     HIPCHK(c, hipMemcpyAsync(out + (long long)k * nc, stage_ptr(c), (size_t)nc * 8, hipMemcpyDeviceToHost,
                              c->stream),

@@ -1,6 +1,7 @@
-// Host emulator of the step kernel (test support for the HIP path).
+// Host emulator of the step kernels (test support for the HIP path).
 //
-// Runs the very phase functions of step_kernel on the CPU, block by block,
+// Runs the very phase functions of the moments and collide kernels on the
+// CPU: the moments pass cell by cell, then the collide pass block by block,
 // with each barrier-separated phase executed for every thread index before
 // the next phase starts.  The CPU tests use it to check the kernel's tiling,
 // halo, ghost-layer and push-streaming logic against the oracle on small
@@ -24,27 +25,35 @@ namespace {
 using namespace lbf;
 
 template <class C, bool M>
-void emulate_step(StepArgs<typename C::S> a) {
-  const Geometry g = step_geometry<C>(*a.P);
+void emulate_step(StepArgs<typename C::S> a, const KParams& P) {
+  const Geometry g = step_geometry<C>(P);
   a.ntx = g.ntx;
   a.nty = g.nty;
   a.chunk = g.chunk;
   a.nblocks = g.nblocks;
+  a.mom = a.aout;
+  for (int cell = 0; cell < (int)P.ncell; ++cell) moment_cell<C>(a, P, cell);
   std::unique_ptr<Smem<C>> smp(new Smem<C>());
   Smem<C>& sm = *smp;
   for (int b = 0; b < g.nblocks; ++b) {
     memset(&sm, 0xff, sizeof sm);  // poison: a read of an unfilled slot shows up as NaN
-    const BlockPos bp = block_pos<C>(a, b);
+    const BlockPos bp = block_pos<C>(a, P, b);
     if (bp.w0 == 0) {
-      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, sm, bp, f, 0);
-      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, sm, bp, f, -1);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, 0);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, -1);
     } else {
-      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, sm, bp, f, bp.w0 - 1);
-      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, sm, bp, f, bp.w0);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
     }
     for (int w = bp.w0; w < bp.w1; ++w) {
-      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, sm, bp, f, w + 1);
-      for (int t = 0; t < C::NT; ++t) process_cell<C, M>(a, sm, bp, t, w);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
+      const bool edge = (w == 0 || w == P.nwn - 1);
+      for (int t = 0; t < C::NT; ++t) {
+        if (edge)
+          process_cell<C, M, true>(a, P, sm, bp, t, w);
+        else
+          process_cell<C, M, false>(a, P, sm, bp, t, w);
+      }
     }
   }
 }
@@ -77,11 +86,10 @@ int run(const lbf_params* prm, const double* phi, const double* T, const double*
     a.pout = popB.data();
     a.ain = auxA.data();
     a.aout = auxB.data();
-    a.P = &P;
     // poison the outputs: every value must be written by the step
     std::fill(popB.begin(), popB.end(), R(NAN));
     std::fill(auxB.begin(), auxB.end(), R(NAN));
-    emulate_step<C, false>(a);
+    emulate_step<C, false>(a, P);
     popA.swap(popB);
     auxA.swap(auxB);
   }
@@ -97,11 +105,11 @@ int run(const lbf_params* prm, const double* phi, const double* T, const double*
       memset(&a, 0, sizeof a);
       a.pin = popA.data();
       a.ain = auxA.data();
+      a.aout = auxB.data();  // scratch for the moments pass
       a.mout = plane.data();
       a.mfield = k;
-      a.P = &P;
       std::fill(plane.begin(), plane.end(), NAN);
-      emulate_step<C, true>(a);
+      emulate_step<C, true>(a, P);
       memcpy(mom_out + (size_t)k * nc, plane.data(), (size_t)nc * 8);
     }
   }

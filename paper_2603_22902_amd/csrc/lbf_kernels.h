@@ -1,7 +1,9 @@
 // HIP kernels of the coupled LB solver and their launchers.
 //
-//   step_kernel     one fused time step (or, with MOMENTS, one macroscopic
-//                   field at the current time level)
+//   moment_kernel   phi_p^n, f_s^n of every cell (first pass of a step)
+//   collide_kernel  finite differences, sources, collisions and push
+//                   streaming (or, with MOMENTS, one macroscopic field at
+//                   the current time level)
 //   init_kernel     equilibrium start from phi, T (and optionally u, p)
 //   diag_kernel     float64 conservation sums, two deterministic passes
 //   widen_kernel    float32 -> float64 copy of one plane for read-back
@@ -35,36 +37,59 @@ template <int DIM, int NP, typename S, typename R>
 using CfgOf = Cfg<DIM, NP, S, R, Tile<DIM, R>::TX, Tile<DIM, R>::TY>;
 
 // ---------------------------------------------------------------------------
-// Fused step
+// One time step: moments pass, then collide pass
 // ---------------------------------------------------------------------------
+constexpr int MOMENT_THREADS = 256;
+
+template <class C>
+__global__ void __launch_bounds__(MOMENT_THREADS)
+    moment_kernel(const typename C::S* __restrict__ pin, const typename C::S* __restrict__ ain,
+                  typename C::S* __restrict__ aout, StepArgs<typename C::S> a,
+                  const KParams* __restrict__ kp) {
+  const KParams& P = *kp;
+  a.pin = pin;
+  a.ain = ain;
+  a.aout = aout;
+  const int cell = blockIdx.x * MOMENT_THREADS + threadIdx.x;
+  if (cell < P.ncell) moment_cell<C>(a, P, cell);
+}
+
 // The buffers are separate kernel parameters so that the compiler knows
-// they are global memory (global rather than flat loads and stores).
+// they are global memory (global rather than flat loads and stores).  The
+// parameter block is a separate restrict pointer too: no store of the
+// kernel can alias it, so its fields are read with scalar loads.
 template <class C, bool MOMENTS>
 __global__ void __launch_bounds__(C::NT)
-    step_kernel(const typename C::S* __restrict__ pin, typename C::S* __restrict__ pout,
-                const typename C::S* __restrict__ ain, typename C::S* __restrict__ aout,
-                double* __restrict__ mout, StepArgs<typename C::S> a) {
+    collide_kernel(const typename C::S* __restrict__ pin, typename C::S* __restrict__ pout,
+                   const typename C::S* __restrict__ ain, typename C::S* __restrict__ aout,
+                   const typename C::S* __restrict__ mom, double* __restrict__ mout,
+                   StepArgs<typename C::S> a, const KParams* __restrict__ kp) {
+  const KParams& P = *kp;
   a.pin = pin;
   a.pout = pout;
   a.ain = ain;
   a.aout = aout;
+  a.mom = mom;
   a.mout = mout;
   __shared__ Smem<C> sm;
-  const BlockPos bp = block_pos<C>(a, blockIdx.x);
+  const BlockPos bp = block_pos<C>(a, P, blockIdx.x);
   const int tid = threadIdx.x;
   if (bp.w0 == 0) {
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, sm, bp, f, 0);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, 0);
     __syncthreads();
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, sm, bp, f, -1);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, -1);
   } else {
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, sm, bp, f, bp.w0 - 1);
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, sm, bp, f, bp.w0);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
   }
   __syncthreads();
   for (int w = bp.w0; w < bp.w1; ++w) {
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, sm, bp, f, w + 1);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
     __syncthreads();
-    process_cell<C, MOMENTS>(a, sm, bp, tid, w);
+    if (w == 0 || w == P.nwn - 1)
+      process_cell<C, MOMENTS, true>(a, P, sm, bp, tid, w);
+    else
+      process_cell<C, MOMENTS, false>(a, P, sm, bp, tid, w);
     __syncthreads();
   }
 }
@@ -287,20 +312,31 @@ inline Geometry step_geometry(const KParams& P) {
   return g;
 }
 
+// Moments pass into the first N + 1 planes of a.aout (passes & 1), then
+// the collide pass, which reads them through a.mom (passes & 2).  In
+// moments mode a.aout is only used as that scratch and a.pout is not
+// touched.
 template <int DIM, int NP, typename S, typename R>
-inline hipError_t launch_step(StepArgs<S> a, const KParams& hostP, hipStream_t s, bool moments) {
+inline hipError_t launch_step(StepArgs<S> a, const KParams& hostP, const KParams* dP, hipStream_t s,
+                              bool moments, int passes) {
   using C = CfgOf<DIM, NP, S, R>;
   const Geometry g = step_geometry<C>(hostP);
   a.ntx = g.ntx;
   a.nty = g.nty;
   a.chunk = g.chunk;
   a.nblocks = g.nblocks;
+  a.mom = a.aout;
+  const int mb = (int)((hostP.ncell + MOMENT_THREADS - 1) / MOMENT_THREADS);
+  if (passes & 1)
+    hipLaunchKernelGGL((moment_kernel<C>), dim3(mb), dim3(MOMENT_THREADS), 0, s, a.pin, a.ain, a.aout,
+                       a, dP);
+  if (!(passes & 2)) return hipGetLastError();
   if (moments)
-    hipLaunchKernelGGL((step_kernel<C, true>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin, a.pout,
-                       a.ain, a.aout, a.mout, a);
+    hipLaunchKernelGGL((collide_kernel<C, true>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin,
+                       a.pout, a.ain, a.aout, a.mom, a.mout, a, dP);
   else
-    hipLaunchKernelGGL((step_kernel<C, false>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin, a.pout,
-                       a.ain, a.aout, a.mout, a);
+    hipLaunchKernelGGL((collide_kernel<C, false>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin,
+                       a.pout, a.ain, a.aout, a.mom, a.mout, a, dP);
   return hipGetLastError();
 }
 

@@ -10,10 +10,12 @@
 namespace lbf {
 
 // P is the host copy of the parameter block (launch geometry), dP the
-// device copy the kernels read.
+// device copy the kernels read.  step launches the moments pass if
+// (passes & 1) and the collide pass if (passes & 2).
 struct Ops {
   hipError_t (*step)(const void* pin, void* pout, const void* ain, void* aout, double* mout,
-                     int mfield, const KParams& P, const KParams* dP, hipStream_t s, bool moments);
+                     int mfield, const KParams& P, const KParams* dP, hipStream_t s, bool moments,
+                     int passes);
   hipError_t (*init)(const KParams& P, const KParams* dP, const double* fields, int has_u,
                      int has_p, void* pop, void* aux, hipStream_t s);
   hipError_t (*diag)(const KParams& P, const KParams* dP, const void* pop, const void* aux,
@@ -37,7 +39,7 @@ const Ops* ops_mix(int dim, int nphase);
   struct OpsImpl_##NAME {                                                                        \
     static hipError_t step(const void* pin, void* pout, const void* ain, void* aout,             \
                            double* mout, int mfield, const KParams& P, const KParams* dP,        \
-                           hipStream_t s, bool moments) {                                        \
+                           hipStream_t s, bool moments, int passes) {                            \
       StepArgs<ST> a;                                                                            \
       a.pin = static_cast<const ST*>(pin);                                                       \
       a.pout = static_cast<ST*>(pout);                                                           \
@@ -45,8 +47,7 @@ const Ops* ops_mix(int dim, int nphase);
       a.aout = static_cast<ST*>(aout);                                                           \
       a.mout = mout;                                                                             \
       a.mfield = mfield;                                                                         \
-      a.P = dP;                                                                                  \
-      return launch_step<DIM, NP, ST, RT>(a, P, s, moments);                                     \
+      return launch_step<DIM, NP, ST, RT>(a, P, dP, s, moments, passes);                         \
     }                                                                                            \
     static hipError_t init(const KParams& P, const KParams* dP, const double* fields, int has_u, \
                            int has_p, void* pop, void* aux, hipStream_t s) {                     \

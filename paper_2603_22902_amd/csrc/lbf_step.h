@@ -1,5 +1,5 @@
-// The fused coupled-LB time step of arXiv:2603.22902, Sec. 3, as the
-// barrier-separated phases of one HIP kernel.
+// The coupled-LB time step of arXiv:2603.22902, Sec. 3, as two HIP kernels:
+// a streaming moments pass and a collide pass of barrier-separated phases.
 //
 // Storage (structure of arrays, x fastest): populations
 // pop[(lattice*Q + i)*ncell + cell], lattice 0 = f, 1..N = g_p, N+1 = h,
@@ -9,13 +9,19 @@
 // q^{n-1} = (rho C_p T D)^{n-1}.  A step reads buffers "in" and writes "out"
 // (push streaming: each cell writes its post-collision values to x + c_i).
 //
-// Work decomposition: a block owns a lateral tile of TX (x TY in 3D) cells
-// and marches along the wall-normal axis (y in 2D, z in 3D) over a chunk of
+// Moments pass (one thread per cell): phi_p^n and f_s^n of every cell from
+// its populations, written into planes 0..N of "out" aux, where the next
+// step finds them as its lagged phi_p^{n-1}, f_s^{n-1}.  The finite
+// differences of the collide pass then read 1 + N planes per neighbour
+// instead of summing (N + 1) Q populations of every halo cell.
+//
+// Collide pass: a block owns a lateral tile of TX (x TY in 3D) cells and
+// marches along the wall-normal axis (y in 2D, z in 3D) over a chunk of
 // layers.  An LDS ring of three layers holds, for the tile plus a one-cell
 // lateral halo, the fields the finite differences need (phi_p, f_s, rho,
-// u^{n-1}) and each cell's rho H and T.  Each layer is filled once (the
-// halo cells' moments are recomputed by neighbouring blocks); ghost layers
-// outside the wall-normal faces are derived from the boundary layer in LDS.
+// u^{n-1}); ghost layers outside the wall-normal faces are derived from
+// the boundary layer in LDS.  Each cell's own rho H and T are recomputed
+// from the h populations it loads for its collision.
 //
 // Every phase is a __host__ __device__ function of an explicit thread index
 // so that the same code also runs in the host emulator used by the CPU
@@ -52,8 +58,6 @@ struct Smem {
   typename C::R fs[3][C::F];
   typename C::R rho[3][C::F];
   typename C::R u[3][C::DIM][C::F];
-  double rhoH[3][C::F];
-  double T[3][C::F];
 };
 
 template <typename S>
@@ -62,12 +66,12 @@ struct StepArgs {
   S* pout;
   const S* ain;
   S* aout;
+  const S* mom;  // phi_p^n, f_s^n planes (the first N + 1 planes of aout)
   double* mout;  // moments mode: one float64 plane
   int mfield;    // moments mode: field id (phi_p, rhoH, T, f_l, rho, u, p, mdot)
   int ntx, nty;  // lateral tiles
   int chunk;     // layers per block
   int nblocks;
-  const KParams* P;  // device copy of the parameter block (scalar loads)
 };
 
 struct BlockPos {
@@ -108,7 +112,8 @@ __host__ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 template <class C>
-__host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, int b) {
+__host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, const KParams& P,
+                                              int b) {
   const int Lg = xcd_remap(b, a.nblocks);
   const int ntiles = a.ntx * a.nty;
   const int chunk_id = Lg / ntiles, tile = Lg % ntiles;
@@ -117,7 +122,7 @@ __host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, 
   bp.ty0 = (tile / a.ntx) * C::TY;
   bp.w0 = chunk_id * a.chunk;
   const int w1 = bp.w0 + a.chunk;
-  bp.w1 = w1 < a.P->nwn ? w1 : a.P->nwn;
+  bp.w1 = w1 < P.nwn ? w1 : P.nwn;
   return bp;
 }
 
@@ -162,32 +167,41 @@ __host__ __device__ inline void invert(const KParams& P, const R* phi, double rh
   }
 }
 
+// Own rho H = sum_i h_i + q^{n-1}/2 (float64) of a cell from its loaded h
+// populations, and T, f_l by eq. (H).
+template <class C>
+__host__ __device__ inline double own_enthalpy(const KParams& P, const typename C::R* phi,
+                                               const typename C::R* hpop, typename C::R qv,
+                                               double& T, double& fl) {
+  double sh = 0.0;
+#pragma unroll
+  for (int i = 0; i < C::Q; ++i) sh += double(hpop[i]);
+  const double rhoH = sh + 0.5 * double(qv);
+  invert<C::NP>(P, phi, rhoH, T, fl);
+  return rhoH;
+}
+
 __host__ __device__ inline double gprime(double x) { return 2.0 * x * (1.0 - x) * (1.0 - 2.0 * x); }
 __host__ __device__ inline float gprime(float x) { return 2.0f * x * (1.0f - x) * (1.0f - 2.0f * x); }
 
 // ---------------------------------------------------------------------------
-// Fill: moments of one footprint cell of a real layer into the LDS ring.
-// phi_p = sum_i g_{i,p} / (1 - D^{n-1}/2); rho H = sum_i h_i + q^{n-1}/2.
+// Moments pass for one cell: phi_p = sum_i g_{i,p} / (1 - D^{n-1}/2),
+// rho H = sum_i h_i + q^{n-1}/2 (float64), f_s = 1 - f_l from eq. (H).
 // Cell indices are 32-bit (the host limits a grid to 2^30 cells); plane
 // offsets k * ncell are formed in 64-bit once per plane.
 // ---------------------------------------------------------------------------
 template <class C>
-__host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
-                                          const BlockPos& bp, int f, int w) {
+__host__ __device__ inline void moment_cell(const StepArgs<typename C::S>& a, const KParams& P,
+                                            int cell) {
   using R = typename C::R;
   using ST = typename C::S;
   constexpr int Q = C::Q, NP = C::NP;
-  const KParams& P = *a.P;
-  const int lx = f % C::LX, ly = f / C::LX;
-  int lat = wrapf(bp.tx0 + lx - 1, P.nx);
-  if (C::DIM == 3) lat += wrapf(bp.ty0 + ly - 1, P.ny) * P.nx;
   const long long nc = P.ncell;
-  const int cell = w * (int)P.area + lat;
   const ST* __restrict__ pin = a.pin;
   const ST* __restrict__ ain = a.ain;
+  ST* __restrict__ aout = a.aout;
   const R div = R(plane(ain, C::A_DIV, nc)[cell]);
   const R qv = R(plane(ain, C::A_Q, nc)[cell]);
-  const int s = slot(w);
   const R idiv = R(1) / (R(1) - R(0.5) * div);
   R phi[NP];
 #pragma unroll
@@ -196,7 +210,6 @@ __host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem
 #pragma unroll
     for (int i = 0; i < Q; ++i) sum += R(plane(pin, (1 + p) * Q + i, nc)[cell]);
     phi[p] = sum * idiv;
-    sm.phi[s][p][f] = phi[p];
   }
   double sh = 0.0;
 #pragma unroll
@@ -204,13 +217,41 @@ __host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem
   const double rhoH = sh + 0.5 * double(qv);
   double T, fl;
   invert<NP>(P, phi, rhoH, T, fl);
-  const R fs = R(1.0 - fl);
+#pragma unroll
+  for (int p = 0; p < NP; ++p) plane(aout, p, nc)[cell] = ST(phi[p]);
+  plane(aout, C::A_FS, nc)[cell] = ST(R(1.0 - fl));
+}
+
+// ---------------------------------------------------------------------------
+// Fill: the finite-difference fields of one footprint cell of a real layer
+// into the LDS ring (phi_p, f_s from the moments pass, rho by eq. (eq2),
+// u^{n-1}).
+// ---------------------------------------------------------------------------
+template <class C>
+__host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, const KParams& P,
+                                          Smem<C>& sm, const BlockPos& bp, int f, int w) {
+  using R = typename C::R;
+  using ST = typename C::S;
+  constexpr int NP = C::NP;
+  const int lx = f % C::LX, ly = f / C::LX;
+  int lat = wrapf(bp.tx0 + lx - 1, P.nx);
+  if (C::DIM == 3) lat += wrapf(bp.ty0 + ly - 1, P.ny) * P.nx;
+  const long long nc = P.ncell;
+  const int cell = w * (int)P.area + lat;
+  const ST* __restrict__ mom = a.mom;
+  const ST* __restrict__ ain = a.ain;
+  const int s = slot(w);
+  R phi[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    phi[p] = R(plane(mom, p, nc)[cell]);
+    sm.phi[s][p][f] = phi[p];
+  }
+  const R fs = R(plane(mom, C::A_FS, nc)[cell]);
   sm.fs[s][f] = fs;
   sm.rho[s][f] = mixture<R, NP>(phi, fs, P.rho_s, P.rho_l);
 #pragma unroll
   for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = R(plane(ain, C::A_U + d, nc)[cell]);
-  sm.rhoH[s][f] = rhoH;
-  sm.T[s][f] = T;
 }
 
 // Ghost layer beyond a wall-normal face (w = -1 or w = nwn), from the
@@ -220,11 +261,9 @@ __host__ __device__ inline void fill_cell(const StepArgs<typename C::S>& a, Smem
 // everything else is copied, except u^{n-1}, which is mirrored at walls
 // (zero on the face) and copied at open faces.
 template <class C>
-__host__ __device__ inline void fill_ghost(const StepArgs<typename C::S>& a, Smem<C>& sm, int f,
-                                           int w) {
+__host__ __device__ inline void fill_ghost(const KParams& P, Smem<C>& sm, int f, int w) {
   using R = typename C::R;
   constexpr int NP = C::NP;
-  const KParams& P = *a.P;
   const int face = (w < 0) ? 0 : 1;
   const int sb = slot(face == 0 ? 0 : P.nwn - 1), s = slot(w);
   if (face == 0 && P.flow_bc[0] == BC_WALL) {
@@ -248,32 +287,31 @@ __host__ __device__ inline void fill_ghost(const StepArgs<typename C::S>& a, Sme
   const R sgn = (face_flow(P, face) == BC_WALL) ? R(-1) : R(1);
 #pragma unroll
   for (int d = 0; d < C::DIM; ++d) sm.u[s][d][f] = sgn * sm.u[sb][d][f];
-  sm.rhoH[s][f] = sm.rhoH[sb][f];
-  sm.T[s][f] = sm.T[sb][f];
 }
 
 template <class C>
-__host__ __device__ inline void fill_layer_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
-                                                const BlockPos& bp, int f, int w) {
-  if (w < 0 || w >= a.P->nwn)
-    fill_ghost<C>(a, sm, f, w);
+__host__ __device__ inline void fill_layer_cell(const StepArgs<typename C::S>& a, const KParams& P,
+                                                Smem<C>& sm, const BlockPos& bp, int f, int w) {
+  if (w < 0 || w >= P.nwn)
+    fill_ghost<C>(P, sm, f, w);
   else
-    fill_cell<C>(a, sm, bp, f, w);
+    fill_cell<C>(a, P, sm, bp, f, w);
 }
 
 // Push of one post-collision population: x + c_i inside the domain gets it;
 // a link leaving through a wall-normal face (face = 0 or 1, return -1)
 // instead stores the face's value for the opposite, incoming direction at
-// this cell.
-template <class C>
+// this cell.  Only the first and last layer (EDGE) have such links; the
+// test is uniform across a block.
+template <class C, bool EDGE>
 __host__ __device__ inline int push_index(const KParams& P, int i, int gx, int gy, int w, int& face) {
   using L = typename C::L;
   const int tw = w + L::cw(i);
-  if (tw < 0 || tw >= P.nwn) {
+  face = -1;
+  if (EDGE && (tw < 0 || tw >= P.nwn)) {
     face = tw < 0 ? 0 : 1;
     return -1;
   }
-  face = -1;
   int lat = wrap1(gx + L::cl0(i), P.nx);
   if (C::DIM == 3) lat += wrap1(gy + L::cl1(i), P.ny) * P.nx;
   return tw * (int)P.area + lat;
@@ -296,16 +334,15 @@ __host__ __device__ inline R cdot(int i, const R* v) {
 // ---------------------------------------------------------------------------
 // Process: steps 3-7 of the time step for the interior cell of thread tid in
 // layer w.  MOMENTS = true writes one macroscopic field instead of the
-// collision.
+// collision; EDGE must be set for the first and last layer.
 // ---------------------------------------------------------------------------
-template <class C, bool MOMENTS>
-__host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, Smem<C>& sm,
-                                             const BlockPos& bp, int tid, int w) {
+template <class C, bool MOMENTS, bool EDGE>
+__host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, const KParams& P,
+                                             Smem<C>& sm, const BlockPos& bp, int tid, int w) {
   using R = typename C::R;
   using ST = typename C::S;  // storage type
   using L = typename C::L;
   constexpr int Q = C::Q, NP = C::NP, DIM = C::DIM;
-  const KParams& P = *a.P;
   const int tx = tid % C::TX, ty = tid / C::TX;
   const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
   if (gx >= P.nx) return;
@@ -325,9 +362,6 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   for (int p = 0; p < NP; ++p) phi[p] = sm.phi[s0][p][fc];
   const R fs = sm.fs[s0][fc];
   const R rho = sm.rho[s0][fc];
-  const double rhoH = sm.rhoH[s0][fc];
-  const double Td = sm.T[s0][fc];
-  const R T = R(Td);
   R psi = R(0);
 #pragma unroll
   for (int p = 0; p < NP; ++p)
@@ -514,17 +548,20 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   const R s0u = w0 * (-R(1.5) * uu);
   const R pr = R(1.0 / 3.0) / (R(1) - w0) * (sf + R(0.5) * S + (tau_f - R(0.5)) * F0 + rho * s0u);
 
+  const int lh = NP + 1;
   if (MOMENTS) {
+    R hpop[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) hpop[i] = R(plane(pin, lh * Q + i, nc)[cell]);
+    double Td, fl;
+    const double rhoH = own_enthalpy<C>(P, phi, hpop, R(plane(ain, C::A_Q, nc)[cell]), Td, fl);
     const int k = a.mfield;
     double v = 0.0;
     if (k < NP) v = double(phi[k]);
     else if (k == NP) v = rhoH;
     else if (k == NP + 1) v = Td;
-    else if (k == NP + 2) {
-      double t2, fl2;
-      invert<NP>(P, phi, rhoH, t2, fl2);
-      v = fl2;
-    } else if (k == NP + 3) v = double(rho);
+    else if (k == NP + 2) v = fl;
+    else if (k == NP + 3) v = double(rho);
     else if (k < NP + 4 + DIM) v = double(u[k - NP - 4]);
     else if (k == NP + 4 + DIM) v = double(pr);
     else v = double(mdot);
@@ -547,8 +584,8 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
     const R fe = (i == 0) ? R(3) * pr * (w0 - R(1)) + rho * si : R(3) * pr * wi + rho * si;
     const R post = fpop[i] - (fpop[i] - fe) * itf + sfac * Fi;
     int face;
-    const int t = push_index<C>(P, i, gx, gy, w, face);
-    if (t >= 0) {
+    const int t = push_index<C, EDGE>(P, i, gx, gy, w, face);
+    if (!EDGE || t >= 0) {
       plane(pout, i, nc)[t] = ST(post);
     } else {
       const int ib = L::opp(i);
@@ -589,8 +626,8 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
       const R ge = wi * phi[p] * (R(1) + R(3) * cu);
       const R post = gpop[i] - (gpop[i] - ge) * itg + gfac * Gi;
       int face;
-      const int t = push_index<C>(P, i, gx, gy, w, face);
-      if (t >= 0) {
+      const int t = push_index<C, EDGE>(P, i, gx, gy, w, face);
+      if (!EDGE || t >= 0) {
         plane(pout, l * Q + i, nc)[t] = ST(post);
       } else {
         const int ib = L::opp(i);
@@ -606,6 +643,14 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
     }
   }
 
+  // Own rho H (float64) and T, eq. (H), from the h populations.
+  R hpop[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) hpop[i] = R(plane(pin, lh * Q + i, nc)[cell]);
+  double Td, fl;
+  const double rhoH = own_enthalpy<C>(P, phi, hpop, R(plane(ain, C::A_Q, nc)[cell]), Td, fl);
+  const R T = R(Td);
+
   // Total-enthalpy LB: h^eq_0 = rhoH - E_ref T + w_0 (E_ref T - 3/2 rho C_p T u.u),
   // h^eq_i = w_i [E_ref T + rho C_p T (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)],
   // H_i = w_i rho C_p T D, tau_h = 3 lambda / E_ref + 1/2.  The rest
@@ -618,10 +663,6 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
   const R ith = R(1) / tau_h;
   const R hfac = R(1) - R(0.5) * ith;
   const R ET = Eref * T, CT = rhocp * T, HD = CT * Ddiv;
-  const int lh = NP + 1;
-  R hpop[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) hpop[i] = R(plane(pin, lh * Q + i, nc)[cell]);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const R wi = wgt<R, DIM>(i);
@@ -640,8 +681,8 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
       post = hpop[i] - (hpop[i] - he) * ith + hfac * (wi * HD);
     }
     int face;
-    const int t = push_index<C>(P, i, gx, gy, w, face);
-    if (t >= 0) {
+    const int t = push_index<C, EDGE>(P, i, gx, gy, w, face);
+    if (!EDGE || t >= 0) {
       plane(pout, lh * Q + i, nc)[t] = ST(post);
     } else {
       const int ib = L::opp(i);
@@ -665,11 +706,9 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, S
     }
   }
 
-  // Lagged fields for the next step.
+  // Lagged fields for the next step (phi_p and f_s were written by the
+  // moments pass).
   ST* __restrict__ aout = a.aout;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) plane(aout, p, nc)[cell] = ST(phi[p]);
-  plane(aout, C::A_FS, nc)[cell] = ST(fs);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) plane(aout, C::A_U + d, nc)[cell] = ST(u[d]);
   plane(aout, C::A_DIV, nc)[cell] = ST(Ddiv);

@@ -63,6 +63,7 @@ def lib():
         L.lbf_create.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.lbf_init_fields.argtypes = [vp, _PD, _PD, _PD, _PD]
         L.lbf_step.argtypes = [vp, ctypes.c_int]
+        L.lbf_step_timed.argtypes = [vp, ctypes.c_int, _PD]
         L.lbf_get_moments.argtypes = [vp, ctypes.c_uint, _PD]
         L.lbf_get_populations.argtypes = [vp, _PD]
         L.lbf_get_aux.argtypes = [vp, _PD]
@@ -77,7 +78,7 @@ def lib():
         L.lbf_status_string.restype = ctypes.c_char_p
         L.lbf_status_string.argtypes = [ctypes.c_int]
         for name in ("lbf_check_params", "lbf_state_bytes", "lbf_create", "lbf_init_fields",
-                     "lbf_step", "lbf_get_moments", "lbf_get_populations", "lbf_get_aux",
+                     "lbf_step", "lbf_step_timed", "lbf_get_moments", "lbf_get_populations", "lbf_get_aux",
                      "lbf_diagnostics", "lbf_snapshot_bytes", "lbf_save_state", "lbf_load_state",
                      "lbf_step_count", "lbf_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -208,6 +209,13 @@ class Solver:
 
     def lbf_step(self, n: int = 1):
         self._check(lib().lbf_step(self._h, int(n)))
+
+    def lbf_step_timed(self, n: int) -> tuple:
+        """n steps; returns the average (moments, collide) kernel durations
+        per step in milliseconds, measured with HIP events on the stream."""
+        ms = np.zeros(2)
+        self._check(lib().lbf_step_timed(self._h, int(n), _ptr(ms)))
+        return float(ms[0]), float(ms[1])
 
     def lbf_get_moments(self, mask: int = LBF_M_ALL) -> dict:
         N, d = self.N, self.dim

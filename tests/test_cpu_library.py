@@ -95,7 +95,7 @@ def test_emulated_kernel_matches_oracle(spec):
     o = oracle.Oracle(case["params"])
     o.init_case(case)
     o.step(n)
-    errs, bad = compare_moments(mom, o.moments(), prec)
+    errs, bad = compare_moments(mom, o.moments(), prec, case["params"])
     assert not bad, errs
     assert rel_err(pop, o.populations(), prec) <= TOL[prec]
     assert rel_err(aux, o.aux(), prec) <= TOL[prec]
@@ -106,3 +106,23 @@ def test_emulated_kernel_under_address_sanitizer():
     r = subprocess.run([emulator.SAN_PATH], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "0 with non-finite output" in r.stdout
+
+
+def test_float32_liquid_fraction_metric_is_well_conditioned():
+    """The parity tests compare float32 runs on psi f_l rather than f_l.  In a
+    gas cell at T = T_melt with a trace psi of freezing material, a relative
+    1e-7 change of rho H (float32 rounding) moves f_l from eq. (H) by far
+    more than the 2e-5 bar, while psi f_l moves by about 1e-7 of its scale,
+    like rho H itself."""
+    case = synth.impurities(n=136, radius=64.0)
+    prm = case["params"]
+    psi = 1e-4
+    phi = [psi, 1.0 - psi, 0.0, 0.0]  # base liquid trace in gas
+    rhoH = oracle.enthalpy(prm, phi, 0.0, 0.5)  # half-way through its (tiny) latent range
+    T0, fl0 = oracle.invert(prm, phi, rhoH)
+    # rounding-size perturbation relative to the field's scale (liquid rho L)
+    scale = prm["rho_l"][0] * prm["latent"][0]
+    T1, fl1 = oracle.invert(prm, phi, rhoH + 1e-7 * scale)
+    assert T0 == T1 == 0.0
+    assert abs(fl1 - fl0) > 10 * TOL["fp32"]
+    assert abs(psi * fl1 - psi * fl0) <= 2e-7
