@@ -172,6 +172,56 @@ lbf_status lbf_snapshot_bytes(const lbf_ctx* ctx, size_t* bytes);
 lbf_status lbf_save_state(lbf_ctx* ctx, void* host, size_t bytes);
 lbf_status lbf_load_state(lbf_ctx* ctx, const void* host, size_t bytes);
 
+/* Device-side state copies (for checkpointing on the GPU).  A device state
+ * is the populations followed by the lagged fields, in the storage type,
+ * lbf_state_device_bytes long.  lbf_state_to_device copies the current state
+ * to dst (asynchronous on the context's stream); lbf_state_from_device makes
+ * src the current state and sets the step count to steps (clears LBF_ENAN). */
+lbf_status lbf_state_device_bytes(const lbf_ctx* ctx, size_t* bytes);
+lbf_status lbf_state_to_device(lbf_ctx* ctx, void* dst);
+lbf_status lbf_state_from_device(lbf_ctx* ctx, const void* src, long long steps);
+
+/* ---- Reverse mode: the discrete adjoint of the Sec. 3 step ----------------
+ * Gradient of the frozen fraction of the freezing material at the final
+ * state, J = sum_x f_s psi / sum_x psi (psi = sum of the freezing phases'
+ * phi_p, f_s and phi_p the moments of the final state), with respect to
+ * T_face[2], latent[4] and cos_theta[4][4] (each entry independent), through
+ * every step of the run and the equilibrium start (lbf_init_fields with u
+ * and p zero).  Built for dim = 2 with LBF_FP32 or LBF_FP64 (LBF_ENOTSUP
+ * otherwise).  The inversion of eq. (H) and the regularised norm of the
+ * pairwise normals are piecewise smooth: the derivative of the branch taken
+ * is used.
+ *
+ * Use: run the forward steps keeping device states x^0..x^K (or checkpoints
+ * and recomputation); with x^K current, lbf_adjoint_seed; then for
+ * n = K-1 .. 0, lbf_adjoint_step with x^n; then lbf_adjoint_finish with x^0
+ * and lbf_adjoint_gradient.  All calls are asynchronous on the context's
+ * stream except seed and gradient, which synchronise it.  The adjoint
+ * context reads the forward context's parameters and stream; it must not
+ * outlive it.  The caller allocates lbf_adjoint_bytes of device memory
+ * (256-byte aligned) and keeps it for the adjoint context's lifetime. */
+typedef struct lbf_adj lbf_adj;
+lbf_status lbf_adjoint_bytes(const lbf_params* prm, size_t* bytes);
+lbf_status lbf_adjoint_create(lbf_ctx* ctx, void* dev_buf, size_t bytes, lbf_adj** out);
+/* Objective of the context's current state into *J (may be NULL); resets
+ * the gradient and sets the adjoint state to dJ/dx^K.  LBF_EINVAL if the
+ * state holds no freezing material. */
+lbf_status lbf_adjoint_seed(lbf_adj* adj, double* J);
+/* One reverse step: state = device state x^n (layout of lbf_state_to_device)
+ * of the step whose output's adjoint is current; afterwards the adjoint of
+ * x^n is current and the step's parameter terms are added. */
+lbf_status lbf_adjoint_step(lbf_adj* adj, const void* state);
+/* Adds the dependence of the equilibrium start x^0 on the latent heats. */
+lbf_status lbf_adjoint_finish(lbf_adj* adj, const void* state0);
+/* grad[22] (float64): [0..1] dJ/dT_face, [2..5] dJ/dlatent,
+ * [6..21] dJ/dcos_theta[p][q] row-major. */
+lbf_status lbf_adjoint_gradient(lbf_adj* adj, double* grad);
+/* Current adjoint state as float64, in the layouts of lbf_get_populations
+ * and lbf_get_aux. */
+lbf_status lbf_adjoint_state(lbf_adj* adj, double* pops, double* aux);
+/* Release the adjoint context (not its buffer).  NULL is a no-op. */
+lbf_status lbf_adjoint_destroy(lbf_adj* adj);
+
 /* Steps taken since lbf_init_fields (restored by lbf_load_state). */
 lbf_status lbf_step_count(const lbf_ctx* ctx, long long* steps);
 

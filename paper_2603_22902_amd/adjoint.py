@@ -1,0 +1,215 @@
+"""Reverse mode of the coupled-LB step (include/lbfreeze.h, lbf_adjoint_*).
+
+Gradient of the frozen fraction of the freezing material at the end of a
+run, J = sum f_s psi / sum psi, with respect to the wall temperatures, the
+latent heats and the wetting cosines, by the hand-written discrete adjoint
+of every step (2D, float32 or float64).  Long runs use checkpoint-and-
+recompute: the forward run keeps the device state every ``window`` steps;
+the reverse sweep re-runs each window forward from its checkpoint, keeping
+its states on the device, and then steps the adjoint back through it.
+
+:class:`FrozenFraction` exposes this as a ``torch.autograd.Function`` of
+(T_w, latent[N], cos_theta[N, N]); derived parameters such as the Stefan
+number (L = C (T_melt - T_w) / Ste) or the contact angle (cos_theta) are
+composed in torch around it.
+"""
+from __future__ import annotations
+
+import copy
+import ctypes
+
+import numpy as np
+
+from .lbfreeze import LBF_OK, LbfError, Solver, _PD, _ptr, lib, make_params
+
+NPAR = 22
+
+
+class Adjoint:
+    """Adjoint context bound to a :class:`Solver` (same device and stream)."""
+
+    def __init__(self, solver: Solver):
+        import torch
+
+        self.solver = solver
+        n = ctypes.c_size_t(0)
+        s = lib().lbf_adjoint_bytes(ctypes.byref(solver._P), ctypes.byref(n))
+        if s != LBF_OK:
+            raise LbfError(s, "lbf_adjoint_bytes: the reverse step needs dim 2 and fp32 or fp64")
+        nbytes = int(n.value)
+        self.buffer = torch.empty(nbytes + 256, dtype=torch.uint8, device=solver.device)
+        aligned = (self.buffer.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p(0)
+        solver._check(lib().lbf_adjoint_create(solver._h, ctypes.c_void_p(aligned), nbytes, ctypes.byref(h)))
+        self._h = h
+
+    def _check(self, s):
+        self.solver._check(s)
+
+    def seed(self) -> float:
+        J = np.zeros(1)
+        self._check(lib().lbf_adjoint_seed(self._h, _ptr(J)))
+        return float(J[0])
+
+    def step(self, state) -> None:
+        self._check(lib().lbf_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr())))
+
+    def finish(self, state0) -> None:
+        self._check(lib().lbf_adjoint_finish(self._h, ctypes.c_void_p(state0.data_ptr())))
+
+    def gradient(self) -> dict:
+        g = np.zeros(NPAR)
+        self._check(lib().lbf_adjoint_gradient(self._h, _ptr(g)))
+        N = self.solver.N
+        return dict(T_face=g[0:2].copy(), latent=g[2:2 + N].copy(),
+                    cos_theta=g[6:22].reshape(4, 4)[:N, :N].copy(), raw=g)
+
+    def state(self):
+        s = self.solver
+        pops = np.empty(((s.N + 2) * s.Q,) + s.shape)
+        aux = np.empty((s.N + s.dim + 3,) + s.shape)
+        self._check(lib().lbf_adjoint_state(self._h, _ptr(pops), _ptr(aux)))
+        return pops, aux
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbf_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _states(solver: Solver, k: int):
+    import torch
+    return torch.empty((k, solver.state_device_bytes()), dtype=torch.uint8, device=solver.device)
+
+
+def forward_with_checkpoints(solver: Solver, case: dict, nsteps: int, window: int):
+    """Equilibrium start from case, nsteps steps; returns the device states
+    at steps 0, window, 2 window, ... (one row each)."""
+    solver.init_case(case)
+    nck = (nsteps + window - 1) // window if nsteps > 0 else 1
+    ck = _states(solver, nck)
+    done = 0
+    for k in range(nck):
+        solver.lbf_state_to_device(ck[k])
+        n = min(window, nsteps - done)
+        if n > 0:
+            solver.lbf_step(n)
+            done += n
+    return ck
+
+
+def reverse_sweep(solver: Solver, ck, nsteps: int, window: int) -> tuple:
+    """With the final state current: J and its gradient (dict) by the
+    reverse steps, re-running each window forward from its checkpoint.
+    Leaves the final state current again."""
+    adj = Adjoint(solver)
+    final = _states(solver, 1)
+    solver.lbf_state_to_device(final[0])
+    J = adj.seed()
+    tape = _states(solver, max(1, min(window, nsteps)))
+    nck = ck.shape[0]
+    for k in range(nck - 1, -1, -1):
+        start = k * window
+        n = min(window, nsteps - start)
+        if n <= 0:
+            continue
+        solver.lbf_state_from_device(ck[k], start)
+        tape[0].copy_(ck[k])
+        for j in range(1, n):
+            solver.lbf_step(1)
+            solver.lbf_state_to_device(tape[j])
+        for j in range(n - 1, -1, -1):
+            adj.step(tape[j])
+    adj.finish(ck[0])
+    g = adj.gradient()
+    solver.lbf_state_from_device(final[0], nsteps)
+    adj.close()
+    return J, g
+
+
+def case_with(case: dict, T_w=None, latent=None, cos_theta=None) -> dict:
+    """A copy of case whose parameters take T_face[0] = T_w, latent[:N] and
+    cos_theta[:N, :N] (plain floats / arrays)."""
+    c = dict(case)
+    prm = copy.deepcopy(case["params"])
+    N = prm["nphase"]
+    if T_w is not None:
+        prm["T_face"] = [float(T_w), float(prm["T_face"][1])]
+    if latent is not None:
+        lat = list(prm["latent"])
+        for p in range(N):
+            lat[p] = float(latent[p])
+        prm["latent"] = lat
+    if cos_theta is not None:
+        ct = [list(r) for r in prm["cos_theta"]]
+        for p in range(N):
+            for q in range(N):
+                ct[p][q] = float(cos_theta[p][q])
+        prm["cos_theta"] = ct
+    c["params"] = prm
+    make_params(prm)  # validates the layout of the dict
+    return c
+
+
+def frozen_fraction_and_gradient(case: dict, nsteps: int, window: int = 50, device: int = 0):
+    """Forward run with checkpoints, then the reverse sweep: (J, gradient)."""
+    s = Solver(case["params"], device=device)
+    ck = forward_with_checkpoints(s, case, nsteps, window)
+    J, g = reverse_sweep(s, ck, nsteps, window)
+    s.close()
+    return J, g
+
+
+def _torch_function():
+    import torch
+
+    class FrozenFraction(torch.autograd.Function):
+        """J = frozen fraction after nsteps, as a function of T_w (0-d),
+        latent (N,) and cos_theta (N, N) float64 CPU tensors.  The forward
+        keeps checkpoints on the GPU; backward runs the reverse sweep."""
+
+        @staticmethod
+        def forward(ctx, T_w, latent, cos_theta, case, nsteps, window, device=0):
+            c = case_with(case, float(T_w), latent.detach().cpu().numpy(),
+                          cos_theta.detach().cpu().numpy())
+            s = Solver(c["params"], device=device)
+            ck = forward_with_checkpoints(s, c, nsteps, window)
+            d = s.lbf_diagnostics()
+            N = s.N
+            frz = [p for p in range(N) if c["params"]["freezes"][p]]
+            area = s.shape[2] * (s.shape[1] if s.dim == 3 else 1)
+            B = float(sum(d["vol"][p] for p in frz))
+            J = d["front"] * area / B
+            ctx.solver, ctx.ck, ctx.nsteps, ctx.window = s, ck, nsteps, window
+            ctx.shapes = (latent.shape, cos_theta.shape)
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            _, g = reverse_sweep(ctx.solver, ctx.ck, ctx.nsteps, ctx.window)
+            N = ctx.solver.N
+            gT = torch.tensor(g["T_face"][0], dtype=torch.float64) * gJ
+            gL = torch.tensor(g["latent"][:N], dtype=torch.float64) * gJ
+            gC = torch.tensor(g["cos_theta"], dtype=torch.float64) * gJ
+            ctx.solver.close()
+            ctx.solver = ctx.ck = None
+            return gT, gL, gC, None, None, None, None
+
+    return FrozenFraction
+
+
+_FF = None
+
+
+def frozen_fraction(T_w, latent, cos_theta, case: dict, nsteps: int, window: int = 50, device: int = 0):
+    """torch entry point: J(T_w, latent, cos_theta) with autograd support."""
+    global _FF
+    if _FF is None:
+        _FF = _torch_function()
+    return _FF.apply(T_w, latent, cos_theta, case, nsteps, window, device)

@@ -2,7 +2,8 @@
 
   liblbfreeze.so       the C-ABI library (include/lbfreeze.h): kernels for
                        float32 and float64 plus the host API
-  liblbfreeze_emu.so   host emulator of the step kernel (CPU tests only)
+  liblbfreeze_emu.so   host emulator of the step and reverse-step kernels
+                       (CPU tests only)
   lbf_emu_sanitize     sanitizer driver of the emulator (CPU tests only)
 
 Usage: ``python -m paper_2603_22902_amd.build`` or ``build()``.  Every call
@@ -52,7 +53,7 @@ def build(verbose: bool = False, emulator: bool = True) -> str:
             jobs.append([HIPCC, *DEV_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         if emulator:
             jobs.append([HIPCC, *HOST_FLAGS, "-O2", "-shared", os.path.join(CSRC, "lbf_emu.hip"),
-                         "-o", EMU + ".tmp"])
+                         os.path.join(CSRC, "lbf_emu_adj.hip"), "-o", EMU + ".tmp"])
             jobs.append([HIPCC, *HOST_FLAGS, "-O1", "-g", "-DLBF_EMU_MAIN",
                          "-Xarch_host", "-fsanitize=address",
                          "-Xarch_host", "-fsanitize=undefined",

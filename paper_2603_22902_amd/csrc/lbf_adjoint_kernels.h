@@ -1,0 +1,149 @@
+// HIP kernels of the reverse (adjoint) step and their launchers.
+//
+//   adj_moment_kernel        pass 1: forward moments of x^n
+//   adj_collide_kernel       pass 2: reverse of the collide pass
+//   adj_gather_kernel        pass 3: transpose of the finite differences and
+//                            of the moments (SEED: start from the objective)
+//   adj_objective_kernel     sums A = sum f_s psi, B = sum psi of a state
+//   adj_seed_kernel          adjoints of phi, f_s of J = A / B
+//   adj_init_latent_kernel   dependence of the initial state on L_p
+//
+// (The block partials are summed into the gradient by a kernel of the API
+// unit, which does not depend on the precision.)
+// One thread per cell, 256-thread blocks.  Each thread's parameter-gradient
+// contributions are summed in a fixed order (wave shuffles, then waves), so
+// a reverse run is deterministic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbf_adjoint.h"
+#include "lbf_kernels.h"
+
+namespace lbf {
+
+constexpr int ADJ_THREADS = 256;
+
+// Sum NV per-thread values over the block into part[blockIdx.x][NV].
+template <int NV>
+__device__ inline void block_sum(const double* g, double* part) {
+  __shared__ double red[ADJ_THREADS / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double v = g[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < ADJ_THREADS / 64; ++w) s += red[w][threadIdx.x];
+    part[(long long)blockIdx.x * NV + threadIdx.x] = s;
+  }
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS)
+    adj_moment_kernel(AdjArgs<C> a, const KParams* __restrict__ kp) {
+  const KParams& P = *kp;
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_moment_cell<C>(a, P, cell);
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS)
+    adj_collide_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
+  const KParams& P = *kp;
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
+  block_sum<NPAR>(g, part);
+}
+
+template <class C, bool SEED>
+__global__ void __launch_bounds__(ADJ_THREADS)
+    adj_gather_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
+  const KParams& P = *kp;
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_gather_cell<C>(a, P, cell, SEED, g);
+  block_sum<NPAR>(g, part);
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS)
+    adj_objective_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
+  using L = AdjLayout<C>;
+  const KParams& P = *kp;
+  double g[2] = {0.0, 0.0};
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) {
+    const long long nc = P.ncell;
+    double psi = 0.0;
+#pragma unroll
+    for (int p = 0; p < C::NP; ++p)
+      if (P.freezes[p]) psi += double(wplane(a, L::M_PHI + p, nc)[cell]);
+    g[0] = double(wplane(a, L::M_FS, nc)[cell]) * psi;
+    g[1] = psi;
+  }
+  block_sum<2>(g, part);
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS)
+    adj_seed_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double A, double B) {
+  const KParams& P = *kp;
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_seed_cell<C>(a, P, cell, A, B);
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS)
+    adj_init_latent_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
+  const KParams& P = *kp;
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_init_latent_cell<C>(a, P, cell, g);
+  block_sum<NPAR>(g, part);
+}
+
+// Launchers.  pass: 0 moments, 1 collide, 2 gather, 3 seed gather,
+// 4 objective partials, 5 seed (A, B), 6 initial-state latent term.
+template <int DIM, int NP, typename S, typename R>
+inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* lpin, const S* lain, S* lpout,
+                                 S* laout, void* work, const KParams& P, const KParams* dP, double* part,
+                                 double A, double B, hipStream_t s) {
+  using C = CfgOf<DIM, NP, S, R>;
+  AdjArgs<C> a;
+  a.pin = pin;
+  a.ain = ain;
+  a.lpin = lpin;
+  a.lain = lain;
+  a.lpout = lpout;
+  a.laout = laout;
+  a.work = static_cast<R*>(work);
+  const int nb = (int)((P.ncell + ADJ_THREADS - 1) / ADJ_THREADS);
+  const dim3 grid(nb), block(ADJ_THREADS);
+  switch (pass) {
+    case 0: hipLaunchKernelGGL((adj_moment_kernel<C>), grid, block, 0, s, a, dP); break;
+    case 1: hipLaunchKernelGGL((adj_collide_kernel<C>), grid, block, 0, s, a, dP, part); break;
+    case 2: hipLaunchKernelGGL((adj_gather_kernel<C, false>), grid, block, 0, s, a, dP, part); break;
+    case 3: hipLaunchKernelGGL((adj_gather_kernel<C, true>), grid, block, 0, s, a, dP, part); break;
+    case 4: hipLaunchKernelGGL((adj_objective_kernel<C>), grid, block, 0, s, a, dP, part); break;
+    case 5: hipLaunchKernelGGL((adj_seed_kernel<C>), grid, block, 0, s, a, dP, A, B); break;
+    case 6: hipLaunchKernelGGL((adj_init_latent_kernel<C>), grid, block, 0, s, a, dP, part); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbf

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/lbfreeze.h"
+#include "lbf_adjoint.h"
 #include "lbf_host.h"
 #include "lbf_ops.h"
 
@@ -27,7 +28,33 @@ struct lbf_ctx {
   std::string err;
 };
 
+struct lbf_adj {
+  lbf_ctx* c;
+  lbf::AdjBufLayout lay;
+  char* base;
+  int cur;  // adjoint buffer holding the adjoint of the current time level
+  bool seeded;
+  double J;
+};
+
 namespace {
+
+static_assert(lbf::NPAR == 22, "the adjoint buffer layout reserves 22 gradient slots");
+
+// Sum per-block partials (nv values per block, in block order) into acc.
+__global__ void adj_reduce_kernel(const double* __restrict__ part, int nblocks, int nv,
+                                  double* __restrict__ acc, int accumulate) {
+  const int k = threadIdx.x;
+  if (k >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += part[(long long)b * nv + k];
+  acc[k] = accumulate ? acc[k] + s : s;
+}
+
+__global__ void adj_zero_kernel(double* __restrict__ x, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) x[k] = 0.0;
+}
 
 constexpr uint64_t kSnapMagic = 0x315A4545524642ULL;  // "BFREEZ1"
 
@@ -387,6 +414,181 @@ lbf_status lbf_load_state(lbf_ctx* c, const void* host, size_t bytes) {
   c->steps = h.steps;
   c->initialized = true;
   c->nan_flag = false;
+  return LBF_OK;
+}
+
+lbf_status lbf_state_device_bytes(const lbf_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return LBF_EINVAL;
+  *bytes = c->lay.pop_bytes + c->lay.aux_bytes;
+  return LBF_OK;
+}
+
+lbf_status lbf_state_to_device(lbf_ctx* c, void* dst) {
+  if (!c) return LBF_EINVAL;
+  if (!dst) return fail(c, LBF_EINVAL, "dst is NULL");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  char* d = static_cast<char*>(dst);
+  HIPCHK(c, hipMemcpyAsync(d, pop_ptr(c, c->cur), c->lay.pop_bytes, hipMemcpyDeviceToDevice, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipMemcpyAsync(d + c->lay.pop_bytes, aux_ptr(c, c->cur), c->lay.aux_bytes, hipMemcpyDeviceToDevice,
+                           c->stream),
+         "hipMemcpyAsync");
+  return LBF_OK;
+}
+
+lbf_status lbf_state_from_device(lbf_ctx* c, const void* src, long long steps) {
+  if (!c) return LBF_EINVAL;
+  if (!src) return fail(c, LBF_EINVAL, "src is NULL");
+  if (steps < 0) return fail(c, LBF_EINVAL, "steps must be >= 0");
+  const char* s = static_cast<const char*>(src);
+  HIPCHK(c, hipMemcpyAsync(pop_ptr(c, c->cur), s, c->lay.pop_bytes, hipMemcpyDeviceToDevice, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipMemcpyAsync(aux_ptr(c, c->cur), s + c->lay.pop_bytes, c->lay.aux_bytes, hipMemcpyDeviceToDevice,
+                           c->stream),
+         "hipMemcpyAsync");
+  c->steps = steps;
+  c->initialized = true;
+  c->nan_flag = false;
+  return LBF_OK;
+}
+
+// ----- reverse step ----------------------------------------------------
+lbf_status lbf_adjoint_bytes(const lbf_params* prm, size_t* bytes) {
+  if (!bytes) return LBF_EINVAL;
+  if (!lbf::check_params(prm).empty()) return LBF_EINVAL;
+  if (prm->dim != 2 || prm->precision == LBF_MIXED) return LBF_ENOTSUP;
+  *bytes = lbf::make_adj_layout(prm, lbf::make_layout(prm)).total;
+  return LBF_OK;
+}
+
+lbf_status lbf_adjoint_create(lbf_ctx* c, void* dev_buf, size_t bytes, lbf_adj** out) {
+  if (!c || !out) return LBF_EINVAL;
+  *out = nullptr;
+  if (!c->ops->adjoint) return fail(c, LBF_ENOTSUP, "the reverse step is built for 2D float32 and float64");
+  const lbf::AdjBufLayout lay = lbf::make_adj_layout(&c->prm, c->lay);
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255))
+    return fail(c, LBF_EINVAL, "adjoint buffer must be 256-byte aligned");
+  if (bytes < lay.total) return fail(c, LBF_ENOMEM, "adjoint buffer smaller than lbf_adjoint_bytes");
+  lbf_adj* a = new (std::nothrow) lbf_adj();
+  if (!a) return LBF_ENOMEM;
+  a->c = c;
+  a->lay = lay;
+  a->base = static_cast<char*>(dev_buf);
+  a->cur = 0;
+  a->seeded = false;
+  a->J = 0.0;
+  *out = a;
+  return LBF_OK;
+}
+
+namespace {
+void* adj_lp(lbf_adj* a, int k) { return a->base + a->lay.off_lp[k]; }
+void* adj_la(lbf_adj* a, int k) { return a->base + a->lay.off_la[k]; }
+void* adj_work(lbf_adj* a) { return a->base + a->lay.off_work; }
+double* adj_part(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_part); }
+double* adj_acc(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_acc); }
+double* adj_obj(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_obj); }
+
+lbf_status adj_pass(lbf_adj* a, int pass, const void* pin, const void* ain, const void* lpin, const void* lain,
+                    void* lpout, void* laout, double A, double B) {
+  lbf_ctx* c = a->c;
+  HIPCHK(c, c->ops->adjoint(pass, pin, ain, lpin, lain, lpout, laout, adj_work(a), c->kp, kp_ptr(c),
+                            adj_part(a), A, B, c->stream),
+         "adjoint kernel");
+  return LBF_OK;
+}
+
+lbf_status adj_reduce(lbf_adj* a, int nv, double* acc, bool accumulate) {
+  lbf_ctx* c = a->c;
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(64), 0, c->stream, adj_part(a), a->lay.nblocks, nv, acc,
+                     accumulate ? 1 : 0);
+  HIPCHK(c, hipGetLastError(), "adjoint reduction");
+  return LBF_OK;
+}
+}  // namespace
+
+#define ADJCHK(expr)                      \
+  do {                                    \
+    const lbf_status s_ = (expr);         \
+    if (s_ != LBF_OK) return s_;          \
+  } while (0)
+
+lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) {
+  if (!a) return LBF_EINVAL;
+  lbf_ctx* c = a->c;
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  const void* pin = pop_ptr(c, c->cur);
+  const void* ain = aux_ptr(c, c->cur);
+  ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
+  ADJCHK(adj_pass(a, 4, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
+  ADJCHK(adj_reduce(a, 2, adj_obj(a), false));
+  double AB[2];
+  HIPCHK(c, hipMemcpyAsync(AB, adj_obj(a), sizeof AB, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (!(AB[1] > 0.0)) return fail(c, LBF_EINVAL, "no freezing material in the state (sum psi = 0)");
+  hipLaunchKernelGGL(adj_zero_kernel, dim3(1), dim3(64), 0, c->stream, adj_acc(a), (int)lbf::NPAR);
+  HIPCHK(c, hipGetLastError(), "adjoint zero");
+  ADJCHK(adj_pass(a, 5, pin, ain, nullptr, nullptr, nullptr, nullptr, AB[0], AB[1]));
+  ADJCHK(adj_pass(a, 3, pin, ain, nullptr, nullptr, adj_lp(a, 0), adj_la(a, 0), 0.0, 0.0));
+  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
+  a->cur = 0;
+  a->seeded = true;
+  a->J = AB[0] / AB[1];
+  if (J) *J = a->J;
+  return LBF_OK;
+}
+
+lbf_status lbf_adjoint_step(lbf_adj* a, const void* state) {
+  if (!a) return LBF_EINVAL;
+  lbf_ctx* c = a->c;
+  if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
+  if (!state) return fail(c, LBF_EINVAL, "state is NULL");
+  const char* pin = static_cast<const char*>(state);
+  const char* ain = pin + c->lay.pop_bytes;
+  const int k = a->cur;
+  ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
+  ADJCHK(adj_pass(a, 1, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0));
+  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
+  ADJCHK(adj_pass(a, 2, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0));
+  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
+  a->cur = 1 - k;
+  return LBF_OK;
+}
+
+lbf_status lbf_adjoint_finish(lbf_adj* a, const void* state0) {
+  if (!a) return LBF_EINVAL;
+  lbf_ctx* c = a->c;
+  if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
+  if (!state0) return fail(c, LBF_EINVAL, "state0 is NULL");
+  const char* pin = static_cast<const char*>(state0);
+  const char* ain = pin + c->lay.pop_bytes;
+  ADJCHK(adj_pass(a, 6, pin, ain, adj_lp(a, a->cur), adj_la(a, a->cur), nullptr, nullptr, 0.0, 0.0));
+  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
+  return LBF_OK;
+}
+
+lbf_status lbf_adjoint_gradient(lbf_adj* a, double* grad) {
+  if (!a) return LBF_EINVAL;
+  lbf_ctx* c = a->c;
+  if (!grad) return fail(c, LBF_EINVAL, "grad is NULL");
+  if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
+  HIPCHK(c, hipMemcpyAsync(grad, adj_acc(a), lbf::NPAR * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  return LBF_OK;
+}
+
+lbf_status lbf_adjoint_state(lbf_adj* a, double* pops, double* aux) {
+  if (!a) return LBF_EINVAL;
+  lbf_ctx* c = a->c;
+  if (!pops || !aux) return fail(c, LBF_EINVAL, "output is NULL");
+  if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
+  ADJCHK(read_back(c, adj_lp(a, a->cur), (long long)c->nlat * c->Q, pops));
+  return read_back(c, adj_la(a, a->cur), c->naux, aux);
+}
+
+lbf_status lbf_adjoint_destroy(lbf_adj* a) {
+  delete a;
   return LBF_OK;
 }
 

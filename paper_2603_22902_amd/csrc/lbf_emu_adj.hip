@@ -1,0 +1,157 @@
+// Host emulator of the reverse (adjoint) step (test support for the HIP
+// path): runs the adjoint pass functions of lbf_adjoint.h on the CPU over a
+// whole forward trajectory held in memory, so that the CPU tests can check
+// the hand-written adjoint against finite differences of the forward step
+// and of the oracle.  Not part of the library's compute path.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/lbfreeze.h"
+#include "lbf_adjoint.h"
+#include "lbf_host.h"
+#include "lbf_kernels.h"
+
+namespace {
+
+using namespace lbf;
+
+template <class C>
+void forward_step(std::vector<typename C::S>& popA, std::vector<typename C::S>& auxA,
+                  std::vector<typename C::S>& popB, std::vector<typename C::S>& auxB, const KParams& P) {
+  StepArgs<typename C::S> a;
+  memset(&a, 0, sizeof a);
+  a.pin = popA.data();
+  a.pout = popB.data();
+  a.ain = auxA.data();
+  a.aout = auxB.data();
+  const Geometry g = step_geometry<C>(P);
+  a.ntx = g.ntx;
+  a.nty = g.nty;
+  a.chunk = g.chunk;
+  a.nblocks = g.nblocks;
+  a.mom = a.aout;
+  for (int cell = 0; cell < (int)P.ncell; ++cell) moment_cell<C>(a, P, cell);
+  std::vector<Smem<C>> smv(1);
+  Smem<C>& sm = smv[0];
+  for (int b = 0; b < g.nblocks; ++b) {
+    const BlockPos bp = block_pos<C>(a, P, b);
+    if (bp.w0 == 0) {
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, 0);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, -1);
+    } else {
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
+    }
+    for (int w = bp.w0; w < bp.w1; ++w) {
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
+      const bool edge = (w == 0 || w == P.nwn - 1);
+      for (int t = 0; t < C::NT; ++t) {
+        if (edge)
+          process_cell<C, false, true>(a, P, sm, bp, t, w);
+        else
+          process_cell<C, false, false>(a, P, sm, bp, t, w);
+      }
+    }
+  }
+}
+
+// Frozen fraction J = sum f_s psi / sum psi of a state, from the moments.
+template <class C>
+void objective(const AdjArgs<C>& a, const KParams& P, double& A, double& B) {
+  using L = AdjLayout<C>;
+  const long long nc = P.ncell;
+  A = B = 0.0;
+  for (long long c = 0; c < nc; ++c) {
+    double psi = 0.0;
+    for (int p = 0; p < C::NP; ++p)
+      if (P.freezes[p]) psi += double(wplane(a, L::M_PHI + p, nc)[c]);
+    A += double(wplane(a, L::M_FS, nc)[c]) * psi;
+    B += psi;
+  }
+}
+
+template <int DIM, int NP, typename S, typename R>
+int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, double* J, double* grad) {
+  using C = CfgOf<DIM, NP, S, R>;
+  const KParams P = make_kparams(prm);
+  const long long nc = P.ncell;
+  const int Q = Lat<DIM>::Q;
+  const size_t npop = (size_t)(NP + 2) * Q * nc, naux = (size_t)(NP + DIM + 3) * nc;
+  std::vector<double> fields((size_t)(NP + 1) * nc);
+  memcpy(fields.data(), phi, (size_t)NP * nc * 8);
+  memcpy(fields.data() + (size_t)NP * nc, T, (size_t)nc * 8);
+  // the whole trajectory: states x^0 .. x^nsteps
+  std::vector<std::vector<S>> pops(nsteps + 1, std::vector<S>(npop)), auxs(nsteps + 1, std::vector<S>(naux));
+  for (long long c = 0; c < nc; ++c) init_cell<DIM, NP, S>(P, fields.data(), 0, 0, pops[0].data(), auxs[0].data(), c);
+  for (int s = 0; s < nsteps; ++s) forward_step<C>(pops[s], auxs[s], pops[s + 1], auxs[s + 1], P);
+
+  std::vector<R> work((size_t)AdjLayout<C>::NWORK * nc);
+  std::vector<S> lpA(npop), laA(naux), lpB(npop), laB(naux);
+  std::vector<double> gpar(NPAR, 0.0);
+  AdjArgs<C> a;
+  a.work = work.data();
+  // seed from the final state
+  a.pin = pops[nsteps].data();
+  a.ain = auxs[nsteps].data();
+  a.lpin = nullptr;
+  a.lain = nullptr;
+  a.lpout = lpA.data();
+  a.laout = laA.data();
+  for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
+  double A, B;
+  objective<C>(a, P, A, B);
+  *J = A / B;
+  for (int c = 0; c < (int)nc; ++c) adj_seed_cell<C>(a, P, c, A, B);
+  for (int c = 0; c < (int)nc; ++c) adj_gather_cell<C>(a, P, c, true, gpar.data());
+  for (int s = nsteps - 1; s >= 0; --s) {
+    a.pin = pops[s].data();
+    a.ain = auxs[s].data();
+    a.lpin = lpA.data();
+    a.lain = laA.data();
+    a.lpout = lpB.data();
+    a.laout = laB.data();
+    std::fill(lpB.begin(), lpB.end(), S(NAN));
+    std::fill(laB.begin(), laB.end(), S(NAN));
+    for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
+    for (int c = 0; c < (int)nc; ++c) adj_collide_cell<C>(a, P, c, gpar.data());
+    for (int c = 0; c < (int)nc; ++c) adj_gather_cell<C>(a, P, c, false, gpar.data());
+    lpA.swap(lpB);
+    laA.swap(laB);
+  }
+  a.pin = pops[0].data();
+  a.ain = auxs[0].data();
+  a.lpin = lpA.data();
+  for (int c = 0; c < (int)nc; ++c) adj_init_latent_cell<C>(a, P, c, gpar.data());
+  for (int k = 0; k < NPAR; ++k) grad[k] = gpar[k];
+  return 0;
+}
+
+template <int DIM, typename S, typename R>
+int run_n(const lbf_params* prm, const double* phi, const double* T, int nsteps, double* J, double* grad) {
+  switch (prm->nphase) {
+    case 1: return run<DIM, 1, S, R>(prm, phi, T, nsteps, J, grad);
+    case 2: return run<DIM, 2, S, R>(prm, phi, T, nsteps, J, grad);
+    case 3: return run<DIM, 3, S, R>(prm, phi, T, nsteps, J, grad);
+    case 4: return run<DIM, 4, S, R>(prm, phi, T, nsteps, J, grad);
+  }
+  return -1;
+}
+
+}  // namespace
+
+// Frozen fraction J after nsteps from an equilibrium start (phi, T; u = 0,
+// p = 0) and its gradient: grad[0..1] d J / d T_face, grad[2..5] d J / d L_p,
+// grad[6..21] d J / d cth[p][q] (row-major, MAXP x MAXP).
+extern "C" int lbf_emu_adjoint(const lbf_params* prm, const double* phi, const double* T, int nsteps,
+                               double* J, double* grad) {
+  if (!check_params(prm).empty() || nsteps < 0) return -1;
+  lbf_params q = *prm;
+  if (q.dim == 2) q.nz = 1;
+  if (q.dim == 2 && q.precision == LBF_FP64) return run_n<2, double, double>(&q, phi, T, nsteps, J, grad);
+  if (q.dim == 2 && q.precision == LBF_FP32) return run_n<2, float, float>(&q, phi, T, nsteps, J, grad);
+  if (q.dim == 3 && q.precision == LBF_FP64) return run_n<3, double, double>(&q, phi, T, nsteps, J, grad);
+  if (q.dim == 3 && q.precision == LBF_FP32) return run_n<3, float, float>(&q, phi, T, nsteps, J, grad);
+  return -2;
+}

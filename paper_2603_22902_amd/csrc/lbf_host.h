@@ -166,4 +166,42 @@ inline Layout make_layout(const lbf_params* P) {
   return L;
 }
 
+// Layout of the caller-provided buffer of the reverse step: two adjoint
+// states (populations, lagged fields), the work planes of the three passes
+// (arithmetic type), per-block partial sums, the gradient accumulator and
+// the objective sums.
+struct AdjBufLayout {
+  size_t off_lp[2], off_la[2], off_work, off_part, off_acc, off_obj, total;
+  int nblocks, nwork;
+};
+
+inline int adj_nwork(int N, int D) { return 2 * N * D + 4 * N + 2 * D + 6; }
+
+inline AdjBufLayout make_adj_layout(const lbf_params* P, const Layout& F) {
+  AdjBufLayout A;
+  const long long ncell = (long long)P->nx * P->ny * (P->dim == 3 ? P->nz : 1);
+  const size_t relt = P->precision == LBF_FP32 ? 4 : 8;
+  A.nblocks = (int)((ncell + 255) / 256);
+  A.nwork = adj_nwork(P->nphase, P->dim);
+  size_t o = 0;
+  for (int k = 0; k < 2; ++k) {
+    A.off_lp[k] = o;
+    o = align256(o + F.pop_bytes);
+  }
+  for (int k = 0; k < 2; ++k) {
+    A.off_la[k] = o;
+    o = align256(o + F.aux_bytes);
+  }
+  A.off_work = o;
+  o = align256(o + (size_t)A.nwork * ncell * relt);
+  A.off_part = o;
+  o = align256(o + (size_t)A.nblocks * 22 * 8);
+  A.off_acc = o;
+  o = align256(o + 22 * 8);
+  A.off_obj = o;
+  o = align256(o + 2 * 8);
+  A.total = o;
+  return A;
+}
+
 }  // namespace lbf

@@ -21,6 +21,11 @@ struct Ops {
   hipError_t (*diag)(const KParams& P, const KParams* dP, const void* pop, const void* aux,
                      double* part, double* out, hipStream_t s);
   hipError_t (*widen)(const void* in, double* out, long long n, hipStream_t s);
+  // Passes of the reverse step (lbf_adjoint_kernels.h); NULL where the
+  // adjoint is not built (3D, float32 storage with float64 arithmetic).
+  hipError_t (*adjoint)(int pass, const void* pin, const void* ain, const void* lpin, const void* lain,
+                        void* lpout, void* laout, void* work, const KParams& P, const KParams* dP,
+                        double* part, double A, double B, hipStream_t s);
 };
 
 // dim 2 or 3, nphase 1..4; NULL if not built.  f32: float32 storage and
@@ -32,8 +37,9 @@ const Ops* ops_mix(int dim, int nphase);
 
 }  // namespace lbf
 
-// Instantiation of one precision's table (used by the two kernel units).
-#define LBF_DEFINE_OPS(NAME, ST, RT)                                                                 \
+// Instantiation of one precision's table (used by the kernel units); ADJ = 1
+// also builds the reverse step for 2D.
+#define LBF_DEFINE_OPS(NAME, ST, RT, ADJ)                                                            \
   namespace lbf {                                                                                \
   template <int DIM, int NP>                                                                     \
   struct OpsImpl_##NAME {                                                                        \
@@ -62,7 +68,20 @@ const Ops* ops_mix(int dim, int nphase);
     static hipError_t widen(const void* in, double* out, long long n, hipStream_t s) {           \
       return launch_widen<ST>(static_cast<const ST*>(in), out, n, s);                            \
     }                                                                                            \
-    static constexpr Ops ops = {&step, &init, &diag, &widen};                                    \
+    static hipError_t adjoint(int pass, const void* pin, const void* ain, const void* lpin,     \
+                              const void* lain, void* lpout, void* laout, void* work,            \
+                              const KParams& P, const KParams* dP, double* part, double A,       \
+                              double B, hipStream_t s) {                                         \
+      if constexpr (ADJ && DIM == 2)                                                             \
+        return launch_adjoint<DIM, NP, ST, RT>(                                                  \
+            pass, static_cast<const ST*>(pin), static_cast<const ST*>(ain),                      \
+            static_cast<const ST*>(lpin), static_cast<const ST*>(lain), static_cast<ST*>(lpout), \
+            static_cast<ST*>(laout), work, P, dP, part, A, B, s);                                \
+      else                                                                                       \
+        return hipErrorNotSupported;                                                             \
+    }                                                                                            \
+    static constexpr Ops ops = {&step, &init, &diag, &widen,                                     \
+                                (ADJ && DIM == 2) ? &adjoint : nullptr};                         \
   };                                                                                             \
   const Ops* NAME(int dim, int nphase) {                                                         \
     static const Ops* table[2][4] = {                                                            \

@@ -64,6 +64,17 @@ def lib():
         L.lbf_init_fields.argtypes = [vp, _PD, _PD, _PD, _PD]
         L.lbf_step.argtypes = [vp, ctypes.c_int]
         L.lbf_step_timed.argtypes = [vp, ctypes.c_int, _PD]
+        L.lbf_state_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbf_state_to_device.argtypes = [vp, vp]
+        L.lbf_state_from_device.argtypes = [vp, vp, ctypes.c_longlong]
+        L.lbf_adjoint_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbf_adjoint_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.lbf_adjoint_seed.argtypes = [vp, _PD]
+        L.lbf_adjoint_step.argtypes = [vp, vp]
+        L.lbf_adjoint_finish.argtypes = [vp, vp]
+        L.lbf_adjoint_gradient.argtypes = [vp, _PD]
+        L.lbf_adjoint_state.argtypes = [vp, _PD, _PD]
+        L.lbf_adjoint_destroy.argtypes = [vp]
         L.lbf_get_moments.argtypes = [vp, ctypes.c_uint, _PD]
         L.lbf_get_populations.argtypes = [vp, _PD]
         L.lbf_get_aux.argtypes = [vp, _PD]
@@ -80,7 +91,10 @@ def lib():
         for name in ("lbf_check_params", "lbf_state_bytes", "lbf_create", "lbf_init_fields",
                      "lbf_step", "lbf_step_timed", "lbf_get_moments", "lbf_get_populations", "lbf_get_aux",
                      "lbf_diagnostics", "lbf_snapshot_bytes", "lbf_save_state", "lbf_load_state",
-                     "lbf_step_count", "lbf_destroy"):
+                     "lbf_step_count", "lbf_destroy", "lbf_state_device_bytes",
+                     "lbf_state_to_device", "lbf_state_from_device", "lbf_adjoint_bytes",
+                     "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_step", "lbf_adjoint_finish",
+                     "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -272,6 +286,19 @@ class Solver:
         n = ctypes.c_longlong(0)
         self._check(lib().lbf_step_count(self._h, ctypes.byref(n)))
         return int(n.value)
+
+    def state_device_bytes(self) -> int:
+        n = ctypes.c_size_t(0)
+        self._check(lib().lbf_state_device_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def lbf_state_to_device(self, dst) -> None:
+        """Copy the current state into dst (a torch uint8 CUDA tensor of
+        state_device_bytes(), contiguous), asynchronously on the stream."""
+        self._check(lib().lbf_state_to_device(self._h, ctypes.c_void_p(dst.data_ptr())))
+
+    def lbf_state_from_device(self, src, steps: int) -> None:
+        self._check(lib().lbf_state_from_device(self._h, ctypes.c_void_p(src.data_ptr()), int(steps)))
 
     # -- convenience ------------------------------------------------------
     def init_case(self, case: dict):

@@ -258,6 +258,22 @@ def small(dim=2, shape=(70, 37), nphase=2, precision="fp64", seed_k=11,
     return _case("small", prm, phi, T, steps)
 
 
+def near_melting(case, T_wall=0.005, T_top=0.025):
+    """The case with a liquid start just above the melting point, T rising
+    linearly from T_wall at the cold wall to T_top at the far face, and no
+    initial flow: freezing starts within the first steps (for short
+    gradient checks of the reverse step)."""
+    c = dict(case)
+    prm = c["params"]
+    x, y, z = grid(prm)
+    wn = y if prm["dim"] == 2 else z
+    nwn = prm["ny"] if prm["dim"] == 2 else prm["nz"]
+    c["T"] = T_MELT + T_wall + (T_top - T_wall) * wn / nwn
+    c.pop("u", None)
+    c.pop("p", None)
+    return c
+
+
 def stress(case, seed_k=99, phi_noise=1e-3, T_band=0.05, u_amp=1e-3, p_amp=1e-4):
     """Perturbed copy of a case that exercises every branch in the first
     steps: U[-phi_noise, phi_noise] on phi (clipped at 0, renormalised so

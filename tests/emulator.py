@@ -27,6 +27,9 @@ def _lib():
         _emu.lbf_emu_run.restype = ctypes.c_int
         _emu.lbf_emu_run.argtypes = [ctypes.POINTER(lbfreeze.lbf_params), _PD, _PD, _PD, _PD,
                                      ctypes.c_int, _PD, _PD, _PD]
+        _emu.lbf_emu_adjoint.restype = ctypes.c_int
+        _emu.lbf_emu_adjoint.argtypes = [ctypes.POINTER(lbfreeze.lbf_params), _PD, _PD, ctypes.c_int,
+                                         _PD, _PD]
     return _emu
 
 
@@ -54,3 +57,18 @@ def run(case, nsteps):
     m = dict(phi=mom[:N], rhoH=mom[N], T=mom[N + 1], fl=mom[N + 2], rho=mom[N + 3],
              u=mom[N + 4:N + 4 + dim], p=mom[N + 4 + dim], mdot=mom[N + 5 + dim])
     return pop, aux, m
+
+
+def adjoint(params, phi, T, nsteps):
+    """Emulated forward run from an equilibrium start (u = p = 0) and the
+    reverse sweep: (J, grad[22]) with J the frozen fraction of the final
+    state and grad as lbf_adjoint_gradient."""
+    P = lbfreeze.make_params(params)
+    J = np.zeros(1)
+    g = np.zeros(22)
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    rc = _lib().lbf_emu_adjoint(ctypes.byref(P), _p(phi), _p(T), int(nsteps), _p(J), _p(g))
+    if rc != 0:
+        raise RuntimeError(f"lbf_emu_adjoint failed ({rc})")
+    return float(J[0]), g

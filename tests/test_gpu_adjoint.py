@@ -1,0 +1,102 @@
+"""GPU reverse step (lbf_adjoint_* through the C ABI): gradients of the
+frozen fraction against the host emulator of the same passes, against
+central differences of the FP64 oracle, across checkpoint windows, in
+float32, and through torch autograd."""
+import math
+
+import numpy as np
+import pytest
+
+import emulator
+import synth
+from adjoint_util import CASES, central, checks, make_case, oracle_J
+
+pytestmark = pytest.mark.gpu
+
+
+def _grad(case, nsteps, window):
+    from paper_2603_22902_amd.adjoint import frozen_fraction_and_gradient
+    return frozen_fraction_and_gradient(case, nsteps, window)
+
+
+@pytest.mark.parametrize("spec", CASES, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
+def test_gpu_adjoint_matches_emulator_fp64(spec):
+    case = make_case(*spec)
+    print("adjoint case", spec, flush=True)
+    J, g = _grad(case, 30, 30)
+    Je, ge = emulator.adjoint(case["params"], case["phi"], case["T"], 30)
+    assert abs(J - Je) <= 1e-13
+    scale = np.abs(ge).max()
+    assert np.abs(g["raw"] - ge).max() <= 1e-10 * scale, (g["raw"], ge)
+
+
+def test_gpu_adjoint_matches_oracle_gradient():
+    case = make_case(*CASES[1])
+    prm = case["params"]
+    n = 20
+    J, g = _grad(case, n, 7)
+    fj = lambda q: oracle_J(case, q, n)
+    for key, idx, h, pick in checks(prm):
+        fd = central(fj, prm, key, idx, h)
+        assert abs(pick(g["raw"]) - fd) <= 1e-4 * abs(fd) + 1e-10, (key, idx, pick(g["raw"]), fd)
+
+
+def test_checkpoint_window_does_not_change_the_gradient():
+    """Recomputation from checkpoints reproduces the states bitwise, so
+    every window gives the same gradient bitwise."""
+    case = make_case(*CASES[0])
+    ref = None
+    for window in (1, 7, 40):
+        J, g = _grad(case, 40, window)
+        if ref is None:
+            ref = (J, g["raw"])
+        assert J == ref[0] and np.array_equal(g["raw"], ref[1]), window
+
+
+def test_float32_adjoint_close_to_float64():
+    """float32 storage and arithmetic: the gradient of the same case within
+    1e-3 relative of the float64 one (measured ~1e-5)."""
+    c64 = make_case(*CASES[0])
+    c32 = make_case(*CASES[0], precision="fp32")
+    _, g64 = _grad(c64, 30, 10)
+    _, g32 = _grad(c32, 30, 10)
+    scale = np.abs(g64["raw"]).max()
+    err = np.abs(g32["raw"] - g64["raw"]).max() / scale
+    print("fp32 vs fp64 gradient", err)
+    assert err <= 1e-3
+
+
+def test_autograd_stefan_number_and_contact_angle():
+    """torch autograd through the reverse step: J(T_w, Ste, theta) with
+    L = C_s (T_melt - T_w) / Ste for the freezing phase and
+    cos_theta = [[0, cos t], [-cos t, 0]]; the gradient against central
+    differences of GPU forward runs, within 1e-4."""
+    import torch
+
+    from paper_2603_22902_amd.adjoint import frozen_fraction
+
+    base = make_case(*CASES[0])
+    prm = base["params"]
+    Cs = prm["cp_s"][0]
+    n = 25
+
+    def J_of(Tw, Ste, th):
+        L = torch.stack([Cs * (synth.T_MELT - Tw) / Ste, torch.zeros((), dtype=torch.float64)])
+        c, s0 = torch.cos(th), torch.zeros((), dtype=torch.float64)
+        ct = torch.stack([torch.stack([s0, c]), torch.stack([-c, s0])])
+        return frozen_fraction(Tw, L, ct, base, n, 10)
+
+    x = [torch.tensor(v, dtype=torch.float64, requires_grad=True)
+         for v in (prm["T_face"][0], 0.1, math.radians(70.0))]
+    J = J_of(*x)
+    J.backward()
+    for k, h in enumerate((1e-6, 1e-6, 1e-6)):
+        xp = [v.detach().clone() for v in x]
+        xm = [v.detach().clone() for v in x]
+        xp[k] += h
+        xm[k] -= h
+        with torch.no_grad():
+            fd = (J_of(*xp).item() - J_of(*xm).item()) / (2 * h)
+        ga = x[k].grad.item()
+        print("autograd", k, ga, fd)
+        assert abs(ga - fd) <= 1e-4 * abs(fd) + 1e-10, (k, ga, fd)
