@@ -110,6 +110,59 @@ def cpu_baseline(case, budget_s: float = 20.0) -> dict:
                       f"({el:.1f} s, OpenMP over cells)"}
 
 
+def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) -> dict:
+    """Forward plus reverse sweep on the compound droplet (512^2 D2Q9, N=3)
+    from a start just above melting, checkpoint every window steps:
+    wall-clock of each part with events on the solver's stream, their
+    ratio, and the gradient of the frozen fraction w.r.t. T_w and Ste
+    (L_p = C_s (T_melt - T_w) / Ste for both freezing phases)."""
+    import torch
+
+    import synth
+    from paper_2603_22902_amd import Solver
+    from paper_2603_22902_amd.adjoint import forward_with_checkpoints, reverse_sweep
+
+    case = synth.near_melting(synth.compound(precision=precision))
+    prm = case["params"]
+    s = Solver(prm)
+    forward_with_checkpoints(s, case, window, window)  # warm-up
+    reverse_sweep(s, forward_with_checkpoints(s, case, window, window), window, window)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(s.stream)
+    ck = forward_with_checkpoints(s, case, nsteps, window)
+    e1.record(s.stream)
+    t = {}
+    J, g = reverse_sweep(s, ck, nsteps, window, timing=t)
+    e2.record(s.stream)
+    torch.cuda.synchronize()
+    fwd, bwd = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    # plain forward steps (no checkpoint copies) for the per-step ratio
+    s.init_case(case)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.lbf_step(nsteps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / nsteps
+    N = prm["nphase"]
+    Tw, Tm = prm["T_face"][0], synth.T_MELT
+    frz = [p for p in range(N) if prm["freezes"][p]]
+    dL = g["latent"]
+    # L_p = C_s,p (T_m - T_w) / Ste (one Stefan number for the freezing phases)
+    ste = prm["cp_s"][frz[0]] * (Tm - Tw) / prm["latent"][frz[0]]
+    dJ_dSte = sum(dL[p] * (-prm["latent"][p] / ste) for p in frz)
+    dJ_dTw = g["T_face"][0] + sum(dL[p] * (-prm["cp_s"][p] / ste) for p in frz)
+    return {"workload": f"compound {prm['nx']}x{prm['ny']} D2Q9 N={N}, start just above melting",
+            "steps": nsteps, "window": window, "precision": precision,
+            "forward_ms": round(fwd, 2), "reverse_ms": round(bwd, 2),
+            "ratio": round(bwd / fwd, 3),
+            "reverse_step_ms": round(t["reverse_ms"] / nsteps, 4),
+            "forward_step_ms": round(step_ms, 4),
+            "ratio_no_recompute": round(t["reverse_ms"] / nsteps / step_ms, 3),
+            "J": J, "dJ_dTw": dJ_dTw, "dJ_dSte": dJ_dSte}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +171,7 @@ def main():
     ap.add_argument("--workload", default="impurities", choices=["impurities", "droplet", "compound", "film"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver's time step runs on one device; "
@@ -189,9 +243,12 @@ def main():
                      "GB/s": round(bpc["step"] * ncell / ((ms_mom + ms_col) * 1e-3) / 1e9, 1),
                      "mlups_kernels_only": round(ncell / ((ms_mom + ms_col) * 1e-3) / 1e6, 2)}},
     }
+    del s
+    torch.cuda.synchronize()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg()
+        print(f"[bench] adjoint leg {out['adjoint']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        del s
-        torch.cuda.synchronize()
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
 

@@ -180,6 +180,11 @@ lbf_status lbf_load_state(lbf_ctx* ctx, const void* host, size_t bytes);
 lbf_status lbf_state_device_bytes(const lbf_ctx* ctx, size_t* bytes);
 lbf_status lbf_state_to_device(lbf_ctx* ctx, void* dst);
 lbf_status lbf_state_from_device(lbf_ctx* ctx, const void* src, long long steps);
+/* One time step from device state src to device state dst (distinct, each
+ * lbf_state_device_bytes), asynchronous on the context's stream; the
+ * context's own state and step count are not touched (recomputation of a
+ * checkpoint window straight into its tape). */
+lbf_status lbf_step_states(lbf_ctx* ctx, const void* src, void* dst);
 
 /* ---- Reverse mode: the discrete adjoint of the Sec. 3 step ----------------
  * Gradient of the frozen fraction of the freezing material at the final

@@ -104,32 +104,48 @@ def forward_with_checkpoints(solver: Solver, case: dict, nsteps: int, window: in
     return ck
 
 
-def reverse_sweep(solver: Solver, ck, nsteps: int, window: int) -> tuple:
+def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = None) -> tuple:
     """With the final state current: J and its gradient (dict) by the
-    reverse steps, re-running each window forward from its checkpoint.
-    Leaves the final state current again."""
+    reverse steps, re-running each window forward from its checkpoint
+    straight into a device tape (the solver's own state is not touched).
+    timing (a dict) receives the milliseconds spent in recomputation and in
+    reverse steps, measured with events on the solver's stream."""
+    import torch
+
+    ev = []
+
+    def mark():
+        if timing is not None:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(solver.stream)
+            ev.append(e)
+
     adj = Adjoint(solver)
-    final = _states(solver, 1)
-    solver.lbf_state_to_device(final[0])
     J = adj.seed()
-    tape = _states(solver, max(1, min(window, nsteps)))
+    tape = _states(solver, max(1, min(window, nsteps) - 1))
     nck = ck.shape[0]
     for k in range(nck - 1, -1, -1):
         start = k * window
         n = min(window, nsteps - start)
         if n <= 0:
             continue
-        solver.lbf_state_from_device(ck[k], start)
-        tape[0].copy_(ck[k])
+        states = [ck[k]] + [tape[j] for j in range(n - 1)]
+        mark()
         for j in range(1, n):
-            solver.lbf_step(1)
-            solver.lbf_state_to_device(tape[j])
+            solver.lbf_step_states(states[j - 1], states[j])
+        mark()
         for j in range(n - 1, -1, -1):
-            adj.step(tape[j])
+            adj.step(states[j])
+        mark()
     adj.finish(ck[0])
     g = adj.gradient()
-    solver.lbf_state_from_device(final[0], nsteps)
     adj.close()
+    if timing is not None:
+        torch.cuda.synchronize(solver.device)
+        rec = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(0, len(ev), 3))
+        rev = sum(ev[i + 1].elapsed_time(ev[i + 2]) for i in range(0, len(ev), 3))
+        timing["recompute_ms"] = rec
+        timing["reverse_ms"] = rev
     return J, g
 
 

@@ -11,8 +11,10 @@
 // (The block partials are summed into the gradient by a kernel of the API
 // unit, which does not depend on the precision.)
 // One thread per cell, 256-thread blocks.  Each thread's parameter-gradient
-// contributions are summed in a fixed order (wave shuffles, then waves), so
-// a reverse run is deterministic.
+// contributions are summed in a fixed order (wave shuffles, then waves) and
+// added to its block's row of a running accumulator; the rows are reduced
+// once, in block order, when the gradient is read.  A reverse run is thus
+// deterministic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,8 +26,10 @@ namespace lbf {
 
 constexpr int ADJ_THREADS = 256;
 
-// Sum NV per-thread values over the block into part[blockIdx.x][NV].
-template <int NV>
+// Sum NV per-thread values over the block into part[blockIdx.x][NV]
+// (ACC: add to the row, which accumulates this block's terms over the
+// reverse steps; else overwrite).
+template <int NV, bool ACC>
 __device__ inline void block_sum(const double* g, double* part) {
   __shared__ double red[ADJ_THREADS / 64][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -41,7 +45,8 @@ __device__ inline void block_sum(const double* g, double* part) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < ADJ_THREADS / 64; ++w) s += red[w][threadIdx.x];
-    part[(long long)blockIdx.x * NV + threadIdx.x] = s;
+    double* dst = part + (long long)blockIdx.x * NV + threadIdx.x;
+    *dst = ACC ? *dst + s : s;
   }
 }
 
@@ -62,7 +67,7 @@ __global__ void __launch_bounds__(ADJ_THREADS)
   for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
   const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
-  block_sum<NPAR>(g, part);
+  block_sum<NPAR, true>(g, part);
 }
 
 template <class C, bool SEED>
@@ -74,7 +79,7 @@ __global__ void __launch_bounds__(ADJ_THREADS)
   for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
   const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (cell < P.ncell) adj_gather_cell<C>(a, P, cell, SEED, g);
-  block_sum<NPAR>(g, part);
+  block_sum<NPAR, true>(g, part);
 }
 
 template <class C>
@@ -93,7 +98,7 @@ __global__ void __launch_bounds__(ADJ_THREADS)
     g[0] = double(wplane(a, L::M_FS, nc)[cell]) * psi;
     g[1] = psi;
   }
-  block_sum<2>(g, part);
+  block_sum<2, false>(g, part);
 }
 
 template <class C>
@@ -113,7 +118,7 @@ __global__ void __launch_bounds__(ADJ_THREADS)
   for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
   const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (cell < P.ncell) adj_init_latent_cell<C>(a, P, cell, g);
-  block_sum<NPAR>(g, part);
+  block_sum<NPAR, true>(g, part);
 }
 
 // Launchers.  pass: 0 moments, 1 collide, 2 gather, 3 seed gather,

@@ -41,14 +41,21 @@ namespace {
 
 static_assert(lbf::NPAR == 22, "the adjoint buffer layout reserves 22 gradient slots");
 
-// Sum per-block partials (nv values per block, in block order) into acc.
-__global__ void adj_reduce_kernel(const double* __restrict__ part, int nblocks, int nv,
-                                  double* __restrict__ acc, int accumulate) {
-  const int k = threadIdx.x;
-  if (k >= nv) return;
+// out[k] = sum over rows b of part[b][k], one 256-thread block per k: each
+// thread sums a strided set of rows in order, then a fixed-shape tree.
+__global__ void __launch_bounds__(256) adj_reduce_kernel(const double* __restrict__ part, int nrows, int nv,
+                                                         double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[(long long)b * nv + k];
-  acc[k] = accumulate ? acc[k] + s : s;
+  for (int b = threadIdx.x; b < nrows; b += 256) s += part[(long long)b * nv + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = red[0];
 }
 
 __global__ void adj_zero_kernel(double* __restrict__ x, int n) {
@@ -436,6 +443,17 @@ lbf_status lbf_state_to_device(lbf_ctx* c, void* dst) {
   return LBF_OK;
 }
 
+lbf_status lbf_step_states(lbf_ctx* c, const void* src, void* dst) {
+  if (!c) return LBF_EINVAL;
+  if (!src || !dst || src == dst) return fail(c, LBF_EINVAL, "src and dst must be distinct device states");
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  HIPCHK(c, c->ops->step(s, d, s + c->lay.pop_bytes, d + c->lay.pop_bytes, nullptr, 0, c->kp, kp_ptr(c),
+                         c->stream, false, 3),
+         "step kernels");
+  return LBF_OK;
+}
+
 lbf_status lbf_state_from_device(lbf_ctx* c, const void* src, long long steps) {
   if (!c) return LBF_EINVAL;
   if (!src) return fail(c, LBF_EINVAL, "src is NULL");
@@ -485,7 +503,10 @@ namespace {
 void* adj_lp(lbf_adj* a, int k) { return a->base + a->lay.off_lp[k]; }
 void* adj_la(lbf_adj* a, int k) { return a->base + a->lay.off_la[k]; }
 void* adj_work(lbf_adj* a) { return a->base + a->lay.off_work; }
+// per-block rows of the gradient accumulator (NPAR each), then the objective
+// partials (2 per block), the reduced gradient and the objective sums
 double* adj_part(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_part); }
+double* adj_opart(lbf_adj* a) { return adj_part(a) + (size_t)a->lay.nblocks * lbf::NPAR; }
 double* adj_acc(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_acc); }
 double* adj_obj(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_obj); }
 
@@ -493,15 +514,14 @@ lbf_status adj_pass(lbf_adj* a, int pass, const void* pin, const void* ain, cons
                     void* lpout, void* laout, double A, double B) {
   lbf_ctx* c = a->c;
   HIPCHK(c, c->ops->adjoint(pass, pin, ain, lpin, lain, lpout, laout, adj_work(a), c->kp, kp_ptr(c),
-                            adj_part(a), A, B, c->stream),
+                            pass == 4 ? adj_opart(a) : adj_part(a), A, B, c->stream),
          "adjoint kernel");
   return LBF_OK;
 }
 
-lbf_status adj_reduce(lbf_adj* a, int nv, double* acc, bool accumulate) {
+lbf_status adj_reduce(lbf_adj* a, const double* part, int nv, double* out) {
   lbf_ctx* c = a->c;
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(64), 0, c->stream, adj_part(a), a->lay.nblocks, nv, acc,
-                     accumulate ? 1 : 0);
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nv), dim3(256), 0, c->stream, part, a->lay.nblocks, nv, out);
   HIPCHK(c, hipGetLastError(), "adjoint reduction");
   return LBF_OK;
 }
@@ -521,16 +541,16 @@ lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) {
   const void* ain = aux_ptr(c, c->cur);
   ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
   ADJCHK(adj_pass(a, 4, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
-  ADJCHK(adj_reduce(a, 2, adj_obj(a), false));
+  ADJCHK(adj_reduce(a, adj_opart(a), 2, adj_obj(a)));
   double AB[2];
   HIPCHK(c, hipMemcpyAsync(AB, adj_obj(a), sizeof AB, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
   if (!(AB[1] > 0.0)) return fail(c, LBF_EINVAL, "no freezing material in the state (sum psi = 0)");
-  hipLaunchKernelGGL(adj_zero_kernel, dim3(1), dim3(64), 0, c->stream, adj_acc(a), (int)lbf::NPAR);
+  const int nz = a->lay.nblocks * lbf::NPAR;
+  hipLaunchKernelGGL(adj_zero_kernel, dim3((nz + 255) / 256), dim3(256), 0, c->stream, adj_part(a), nz);
   HIPCHK(c, hipGetLastError(), "adjoint zero");
   ADJCHK(adj_pass(a, 5, pin, ain, nullptr, nullptr, nullptr, nullptr, AB[0], AB[1]));
   ADJCHK(adj_pass(a, 3, pin, ain, nullptr, nullptr, adj_lp(a, 0), adj_la(a, 0), 0.0, 0.0));
-  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
   a->cur = 0;
   a->seeded = true;
   a->J = AB[0] / AB[1];
@@ -548,9 +568,7 @@ lbf_status lbf_adjoint_step(lbf_adj* a, const void* state) {
   const int k = a->cur;
   ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
   ADJCHK(adj_pass(a, 1, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0));
-  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
   ADJCHK(adj_pass(a, 2, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0));
-  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
   a->cur = 1 - k;
   return LBF_OK;
 }
@@ -563,7 +581,6 @@ lbf_status lbf_adjoint_finish(lbf_adj* a, const void* state0) {
   const char* pin = static_cast<const char*>(state0);
   const char* ain = pin + c->lay.pop_bytes;
   ADJCHK(adj_pass(a, 6, pin, ain, adj_lp(a, a->cur), adj_la(a, a->cur), nullptr, nullptr, 0.0, 0.0));
-  ADJCHK(adj_reduce(a, lbf::NPAR, adj_acc(a), true));
   return LBF_OK;
 }
 
@@ -572,6 +589,7 @@ lbf_status lbf_adjoint_gradient(lbf_adj* a, double* grad) {
   lbf_ctx* c = a->c;
   if (!grad) return fail(c, LBF_EINVAL, "grad is NULL");
   if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
+  ADJCHK(adj_reduce(a, adj_part(a), lbf::NPAR, adj_acc(a)));
   HIPCHK(c, hipMemcpyAsync(grad, adj_acc(a), lbf::NPAR * sizeof(double), hipMemcpyDeviceToHost, c->stream),
          "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");

@@ -195,7 +195,7 @@ inline AdjBufLayout make_adj_layout(const lbf_params* P, const Layout& F) {
   A.off_work = o;
   o = align256(o + (size_t)A.nwork * ncell * relt);
   A.off_part = o;
-  o = align256(o + (size_t)A.nblocks * 22 * 8);
+  o = align256(o + (size_t)A.nblocks * (22 + 2) * 8);
   A.off_acc = o;
   o = align256(o + 22 * 8);
   A.off_obj = o;

@@ -67,6 +67,7 @@ def lib():
         L.lbf_state_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_state_to_device.argtypes = [vp, vp]
         L.lbf_state_from_device.argtypes = [vp, vp, ctypes.c_longlong]
+        L.lbf_step_states.argtypes = [vp, vp, vp]
         L.lbf_adjoint_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_adjoint_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.lbf_adjoint_seed.argtypes = [vp, _PD]
@@ -92,7 +93,7 @@ def lib():
                      "lbf_step", "lbf_step_timed", "lbf_get_moments", "lbf_get_populations", "lbf_get_aux",
                      "lbf_diagnostics", "lbf_snapshot_bytes", "lbf_save_state", "lbf_load_state",
                      "lbf_step_count", "lbf_destroy", "lbf_state_device_bytes",
-                     "lbf_state_to_device", "lbf_state_from_device", "lbf_adjoint_bytes",
+                     "lbf_state_to_device", "lbf_state_from_device", "lbf_step_states", "lbf_adjoint_bytes",
                      "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_step", "lbf_adjoint_finish",
                      "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -299,6 +300,12 @@ class Solver:
 
     def lbf_state_from_device(self, src, steps: int) -> None:
         self._check(lib().lbf_state_from_device(self._h, ctypes.c_void_p(src.data_ptr()), int(steps)))
+
+    def lbf_step_states(self, src, dst) -> None:
+        """One step from device state src to device state dst (torch uint8
+        tensors of state_device_bytes()); the context's state is untouched."""
+        self._check(lib().lbf_step_states(self._h, ctypes.c_void_p(src.data_ptr()),
+                                          ctypes.c_void_p(dst.data_ptr())))
 
     # -- convenience ------------------------------------------------------
     def init_case(self, case: dict):
