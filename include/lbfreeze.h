@@ -199,8 +199,8 @@ lbf_status lbf_step_states(lbf_ctx* ctx, const void* src, void* dst);
  *
  * Use: run the forward steps keeping device states x^0..x^K (or checkpoints
  * and recomputation); with x^K current, lbf_adjoint_seed; then for
- * n = K-1 .. 0, lbf_adjoint_step with x^n; then lbf_adjoint_finish with x^0
- * and lbf_adjoint_gradient.  All calls are asynchronous on the context's
+ * n = K-1 .. 0, lbf_adjoint_step with x^n (and x^{n+1}); then
+ * lbf_adjoint_finish with x^0 and lbf_adjoint_gradient.  All calls are asynchronous on the context's
  * stream except seed and gradient, which synchronise it.  The adjoint
  * context reads the forward context's parameters and stream; it must not
  * outlive it.  The caller allocates lbf_adjoint_bytes of device memory
@@ -214,8 +214,10 @@ lbf_status lbf_adjoint_create(lbf_ctx* ctx, void* dev_buf, size_t bytes, lbf_adj
 lbf_status lbf_adjoint_seed(lbf_adj* adj, double* J);
 /* One reverse step: state = device state x^n (layout of lbf_state_to_device)
  * of the step whose output's adjoint is current; afterwards the adjoint of
- * x^n is current and the step's parameter terms are added. */
-lbf_status lbf_adjoint_step(lbf_adj* adj, const void* state);
+ * x^n is current and the step's parameter terms are added.  next = the
+ * device state x^{n+1} = step(x^n), or NULL: its lagged fields hold the
+ * moments of x^n, which are otherwise recomputed (one more pass). */
+lbf_status lbf_adjoint_step(lbf_adj* adj, const void* state, const void* next);
 /* Adds the dependence of the equilibrium start x^0 on the latent heats. */
 lbf_status lbf_adjoint_finish(lbf_adj* adj, const void* state0);
 /* grad[22] (float64): [0..1] dJ/dT_face, [2..5] dJ/dlatent,

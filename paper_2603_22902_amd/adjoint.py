@@ -51,8 +51,11 @@ class Adjoint:
         self._check(lib().lbf_adjoint_seed(self._h, _ptr(J)))
         return float(J[0])
 
-    def step(self, state) -> None:
-        self._check(lib().lbf_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr())))
+    def step(self, state, next_state=None) -> None:
+        """Reverse step through x^n = state; next_state = x^{n+1} if at
+        hand (saves recomputing the moments of x^n)."""
+        nxt = ctypes.c_void_p(next_state.data_ptr()) if next_state is not None else None
+        self._check(lib().lbf_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()), nxt))
 
     def finish(self, state0) -> None:
         self._check(lib().lbf_adjoint_finish(self._h, ctypes.c_void_p(state0.data_ptr())))
@@ -122,6 +125,8 @@ def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = N
 
     adj = Adjoint(solver)
     J = adj.seed()
+    final = _states(solver, 1)
+    solver.lbf_state_to_device(final[0])
     tape = _states(solver, max(1, min(window, nsteps) - 1))
     nck = ck.shape[0]
     for k in range(nck - 1, -1, -1):
@@ -129,13 +134,14 @@ def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = N
         n = min(window, nsteps - start)
         if n <= 0:
             continue
-        states = [ck[k]] + [tape[j] for j in range(n - 1)]
+        nxt = ck[k + 1] if start + n < nsteps else final[0]
+        states = [ck[k]] + [tape[j] for j in range(n - 1)] + [nxt]
         mark()
         for j in range(1, n):
             solver.lbf_step_states(states[j - 1], states[j])
         mark()
         for j in range(n - 1, -1, -1):
-            adj.step(states[j])
+            adj.step(states[j], states[j + 1])
         mark()
     adj.finish(ck[0])
     g = adj.gradient()

@@ -8,11 +8,19 @@
 //   lambda^n = (dS/dx^n)^T lambda^{n+1},
 // and adds lambda^{n+1} . dS/dtheta to the parameter gradient.  The state is
 // the populations (f, g_p, h) and the lagged fields (phi_p, f_s, u, D, q), in
-// the forward layout; the adjoint buffers use the same layout.
+// the forward layout; the adjoint buffers use the same layout, except that
+// the adjoint of the lagged fields carries N + 1 more planes: the moments
+// reverse adds one value per cell to every g_{i,p} (phi_p's adjoint over
+// 1 - D/2) and to every h_i (rho H's adjoint).  These stay as the per-cell
+// scalars A_GS + p and A_GS + N, and every reader of a population adjoint
+// adds them (adj_pop), instead of a read-modify-write of all (N+1) Q values.
 //
 // A reverse step is three passes over the cells (one thread per cell):
 //   1. adj_moment_cell   the forward moments phi_p, f_s, rho H of x^n
-//                        (recomputed from the stored state);
+//                        (recomputed from the stored state; skipped when
+//                        x^{n+1} is at hand, whose first N + 1 lagged planes
+//                        are phi_p^n, f_s^n, with rho H then written by
+//                        pass 2);
 //   2. adj_collide_cell  the transpose of the push (each cell pulls the
 //                        adjoints of the values it wrote, including the
 //                        face links), then the reverse of the collisions,
@@ -71,11 +79,43 @@ struct AdjArgs {
   S* lpout;       // adjoint of x^n
   S* laout;
   R* work;        // AdjLayout planes
+  const S* mom;   // lagged fields of x^{n+1} (phi_p^n, f_s^n), or NULL: the
+                  // moment planes of work
 };
 
 template <class C>
 __host__ __device__ inline typename C::R* wplane(const AdjArgs<C>& a, int k, long long nc) {
   return a.work + (long long)k * nc;
+}
+
+// Planes of the per-cell population scalars in the adjoint of the lagged
+// fields (after the N + DIM + 3 planes of the forward layout).
+template <class C>
+struct AdjScal {
+  static constexpr int GS = C::NAUX, HS = C::NAUX + C::NP, NLA = C::NAUX + C::NP + 1;
+};
+
+// Adjoint of population i of lattice l at a cell: the stored value plus the
+// cell's scalar of that lattice (none for f).
+template <class C>
+__host__ __device__ inline typename C::R adj_pop(const typename C::S* lp, const typename C::S* la, int l, int i,
+                                                 int cell, long long nc) {
+  using R = typename C::R;
+  R v = R(plane(lp, l * C::Q + i, nc)[cell]);
+  if (l >= 1) v += R(plane(la, AdjScal<C>::GS + l - 1, nc)[cell]);
+  return v;
+}
+
+// phi_p and f_s of x^n at a cell.
+template <class C>
+__host__ __device__ inline typename C::R m_phi(const AdjArgs<C>& a, int p, int cell, long long nc) {
+  using R = typename C::R;
+  return a.mom ? R(plane(a.mom, p, nc)[cell]) : wplane(a, AdjLayout<C>::M_PHI + p, nc)[cell];
+}
+template <class C>
+__host__ __device__ inline typename C::R m_fs(const AdjArgs<C>& a, int cell, long long nc) {
+  using R = typename C::R;
+  return a.mom ? R(plane(a.mom, C::A_FS, nc)[cell]) : wplane(a, AdjLayout<C>::M_FS, nc)[cell];
 }
 
 __host__ __device__ inline double gsecond(double x) { return 2.0 - 12.0 * x + 12.0 * x * x; }
@@ -193,8 +233,8 @@ __host__ __device__ inline void nb_fields(const AdjArgs<C>& a, const KParams& P,
   const int bw = ghost ? (face == 0 ? 0 : P.nwn - 1) : tw;
   const int b = bw * (int)P.area + lat;
   R pb[NP];
-  for (int p = 0; p < NP; ++p) pb[p] = wplane(a, L::M_PHI + p, nc)[b];
-  fs = wplane(a, L::M_FS, nc)[b];
+  for (int p = 0; p < NP; ++p) pb[p] = m_phi<C>(a, p, b, nc);
+  fs = m_fs<C>(a, b, nc);
   rho = mixture<R, NP>(pb, fs, P.rho_s, P.rho_l);
   const R sgn = (ghost && face_flow(P, face) == BC_WALL) ? R(-1) : R(1);
   for (int d = 0; d < C::DIM; ++d) up[d] = sgn * R(plane(a.ain, C::A_U + d, nc)[b]);
@@ -231,8 +271,8 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
 
   // ---- forward recompute (as process_cell) ----
   R phi[NP];
-  for (int p = 0; p < NP; ++p) phi[p] = wplane(a, L::M_PHI + p, nc)[cell];
-  const R fs = wplane(a, L::M_FS, nc)[cell];
+  for (int p = 0; p < NP; ++p) phi[p] = m_phi<C>(a, p, cell, nc);
+  const R fs = m_fs<C>(a, cell, nc);
   const R rho = mixture<R, NP>(phi, fs, P.rho_s, P.rho_l);
   R psi = R(0);
   for (int p = 0; p < NP; ++p)
@@ -413,8 +453,8 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     int f2;
     const int t = push_index<C, true>(P, i, gx, gy, w, f2);
     face = f2;
-    if (t >= 0) return R(plane(lpin, lattice * Q + i, nc)[t]);
-    return R(plane(lpin, lattice * Q + Lt::opp(i), nc)[cell]);
+    if (t >= 0) return adj_pop<C>(lpin, lain, lattice, i, t, nc);
+    return adj_pop<C>(lpin, lain, lattice, Lt::opp(i), cell, nc);
   };
 
   // -- enthalpy LB and its face rules --
@@ -793,6 +833,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   wplane(a, L::O_FS, nc)[cell] = fsb;
   wplane(a, L::L_FS, nc)[cell] = fspb;
   wplane(a, L::L_Q, nc)[cell] = qpb;
+  wplane(a, L::M_RHOH, nc)[cell] = R(rhoH);  // for pass 3 of this cell
 }
 
 // ---------------------------------------------------------------------------
@@ -816,8 +857,8 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
   const int gx = lat % P.nx, gy = lat / P.nx;
 
   R phi[NP];
-  for (int p = 0; p < NP; ++p) phi[p] = wplane(a, L::M_PHI + p, nc)[cell];
-  const R fs = wplane(a, L::M_FS, nc)[cell];
+  for (int p = 0; p < NP; ++p) phi[p] = m_phi<C>(a, p, cell, nc);
+  const R fs = m_fs<C>(a, cell, nc);
   const double rhoH = double(wplane(a, L::M_RHOH, nc)[cell]);
 
   R phib[NP], fsb = wplane(a, L::O_FS, nc)[cell], rhob = R(0), upb[DIM];
@@ -920,19 +961,12 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
   const R idiv = R(1) / (R(1) - R(0.5) * div);
   R Db = R(0);
   for (int p = 0; p < NP; ++p) {
-    const R gsc = phib[p] * idiv;
     Db += phib[p] * phi[p] * R(0.5) * idiv;
-    for (int i = 0; i < Q; ++i) {
-      ST* g = plane(a.lpout, (1 + p) * Q + i, nc) + cell;
-      *g = seed ? ST(gsc) : ST(R(*g) + gsc);
-    }
+    plane(a.laout, AdjScal<C>::GS + p, nc)[cell] = ST(phib[p] * idiv);
   }
-  for (int i = 0; i < Q; ++i) {
-    ST* h = plane(a.lpout, (NP + 1) * Q + i, nc) + cell;
-    *h = seed ? ST(R(rhoHb)) : ST(R(*h) + R(rhoHb));
-  }
+  plane(a.laout, AdjScal<C>::HS, nc)[cell] = ST(R(rhoHb));
   if (seed)
-    for (int i = 0; i < Q; ++i) plane(a.lpout, i, nc)[cell] = ST(0);
+    for (int k = 0; k < (NP + 2) * Q; ++k) plane(a.lpout, k, nc)[cell] = ST(0);
   const R qb = (seed ? R(0) : wplane(a, L::L_Q, nc)[cell]) + R(0.5 * rhoHb);
   for (int p = 0; p < NP; ++p) plane(a.laout, p, nc)[cell] = seed ? ST(0) : ST(wplane(a, L::L_PHI + p, nc)[cell]);
   plane(a.laout, C::A_FS, nc)[cell] = seed ? ST(0) : ST(wplane(a, L::L_FS, nc)[cell]);
@@ -968,7 +1002,7 @@ __host__ __device__ inline void adj_init_latent_cell(const AdjArgs<C>& a, const 
                                                      double* gpar) {
   constexpr int Q = C::Q, NP = C::NP;
   const long long nc = P.ncell;
-  const double lh0 = double(plane(a.lpin, (NP + 1) * Q, nc)[cell]);
+  const double lh0 = double(adj_pop<C>(a.lpin, a.lain, NP + 1, 0, cell, nc));
   const double fl = 1.0 - double(plane(a.ain, C::A_FS, nc)[cell]);
 #pragma unroll
   for (int p = 0; p < NP; ++p)

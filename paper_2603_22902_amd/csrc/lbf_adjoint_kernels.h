@@ -58,8 +58,10 @@ __global__ void __launch_bounds__(ADJ_THREADS)
   if (cell < P.ncell) adj_moment_cell<C>(a, P, cell);
 }
 
+// The collide reverse holds the forward recompute and the whole reverse of a
+// cell; capped at 256 registers (two waves per SIMD), the gather at 128.
 template <class C>
-__global__ void __launch_bounds__(ADJ_THREADS)
+__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     adj_collide_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
   const KParams& P = *kp;
   double g[NPAR];
@@ -71,7 +73,7 @@ __global__ void __launch_bounds__(ADJ_THREADS)
 }
 
 template <class C, bool SEED>
-__global__ void __launch_bounds__(ADJ_THREADS)
+__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
     adj_gather_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
   const KParams& P = *kp;
   double g[NPAR];
@@ -125,8 +127,8 @@ __global__ void __launch_bounds__(ADJ_THREADS)
 // 4 objective partials, 5 seed (A, B), 6 initial-state latent term.
 template <int DIM, int NP, typename S, typename R>
 inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* lpin, const S* lain, S* lpout,
-                                 S* laout, void* work, const KParams& P, const KParams* dP, double* part,
-                                 double A, double B, hipStream_t s) {
+                                 S* laout, const S* mom, void* work, const KParams& P, const KParams* dP,
+                                 double* part, double A, double B, hipStream_t s) {
   using C = CfgOf<DIM, NP, S, R>;
   AdjArgs<C> a;
   a.pin = pin;
@@ -135,6 +137,7 @@ inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* 
   a.lain = lain;
   a.lpout = lpout;
   a.laout = laout;
+  a.mom = mom;
   a.work = static_cast<R*>(work);
   const int nb = (int)((P.ncell + ADJ_THREADS - 1) / ADJ_THREADS);
   const dim3 grid(nb), block(ADJ_THREADS);

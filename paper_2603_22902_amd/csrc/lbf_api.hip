@@ -511,9 +511,9 @@ double* adj_acc(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.
 double* adj_obj(lbf_adj* a) { return reinterpret_cast<double*>(a->base + a->lay.off_obj); }
 
 lbf_status adj_pass(lbf_adj* a, int pass, const void* pin, const void* ain, const void* lpin, const void* lain,
-                    void* lpout, void* laout, double A, double B) {
+                    void* lpout, void* laout, double A, double B, const void* mom = nullptr) {
   lbf_ctx* c = a->c;
-  HIPCHK(c, c->ops->adjoint(pass, pin, ain, lpin, lain, lpout, laout, adj_work(a), c->kp, kp_ptr(c),
+  HIPCHK(c, c->ops->adjoint(pass, pin, ain, lpin, lain, lpout, laout, mom, adj_work(a), c->kp, kp_ptr(c),
                             pass == 4 ? adj_opart(a) : adj_part(a), A, B, c->stream),
          "adjoint kernel");
   return LBF_OK;
@@ -558,17 +558,18 @@ lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) {
   return LBF_OK;
 }
 
-lbf_status lbf_adjoint_step(lbf_adj* a, const void* state) {
+lbf_status lbf_adjoint_step(lbf_adj* a, const void* state, const void* next) {
   if (!a) return LBF_EINVAL;
   lbf_ctx* c = a->c;
   if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
   if (!state) return fail(c, LBF_EINVAL, "state is NULL");
   const char* pin = static_cast<const char*>(state);
   const char* ain = pin + c->lay.pop_bytes;
+  const char* mom = next ? static_cast<const char*>(next) + c->lay.pop_bytes : nullptr;
   const int k = a->cur;
-  ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
-  ADJCHK(adj_pass(a, 1, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0));
-  ADJCHK(adj_pass(a, 2, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0));
+  if (!mom) ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
+  ADJCHK(adj_pass(a, 1, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0, mom));
+  ADJCHK(adj_pass(a, 2, pin, ain, adj_lp(a, k), adj_la(a, k), adj_lp(a, 1 - k), adj_la(a, 1 - k), 0.0, 0.0, mom));
   a->cur = 1 - k;
   return LBF_OK;
 }
@@ -602,7 +603,23 @@ lbf_status lbf_adjoint_state(lbf_adj* a, double* pops, double* aux) {
   if (!pops || !aux) return fail(c, LBF_EINVAL, "output is NULL");
   if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
   ADJCHK(read_back(c, adj_lp(a, a->cur), (long long)c->nlat * c->Q, pops));
-  return read_back(c, adj_la(a, a->cur), c->naux, aux);
+  ADJCHK(read_back(c, adj_la(a, a->cur), c->naux, aux));
+  // add each cell's population scalars (g_p: plane naux + p, h: naux + N)
+  const long long nc = c->ncell;
+  double* sc = new (std::nothrow) double[(size_t)(c->N + 1) * nc];
+  if (!sc) return fail(c, LBF_ENOMEM, "host scratch");
+  const size_t elt = c->lay.elt;
+  const lbf_status s = read_back(c, static_cast<char*>(adj_la(a, a->cur)) + (size_t)c->naux * nc * elt,
+                                 c->N + 1, sc);
+  if (s == LBF_OK)
+    for (int l = 1; l <= c->N + 1; ++l)
+      for (int i = 0; i < c->Q; ++i) {
+        double* dst = pops + ((long long)l * c->Q + i) * nc;
+        const double* add = sc + (long long)(l - 1) * nc;
+        for (long long k = 0; k < nc; ++k) dst[k] += add[k];
+      }
+  delete[] sc;
+  return s;
 }
 
 lbf_status lbf_adjoint_destroy(lbf_adj* a) {

@@ -88,13 +88,15 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, d
   for (int s = 0; s < nsteps; ++s) forward_step<C>(pops[s], auxs[s], pops[s + 1], auxs[s + 1], P);
 
   std::vector<R> work((size_t)AdjLayout<C>::NWORK * nc);
-  std::vector<S> lpA(npop), laA(naux), lpB(npop), laB(naux);
+  const size_t nla = (size_t)AdjScal<C>::NLA * nc;
+  std::vector<S> lpA(npop), laA(nla), lpB(npop), laB(nla);
   std::vector<double> gpar(NPAR, 0.0);
   AdjArgs<C> a;
   a.work = work.data();
   // seed from the final state
   a.pin = pops[nsteps].data();
   a.ain = auxs[nsteps].data();
+  a.mom = nullptr;
   a.lpin = nullptr;
   a.lain = nullptr;
   a.lpout = lpA.data();
@@ -114,7 +116,11 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, d
     a.laout = laB.data();
     std::fill(lpB.begin(), lpB.end(), S(NAN));
     std::fill(laB.begin(), laB.end(), S(NAN));
-    for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
+    // moments of x^n from x^{n+1}'s lagged fields on odd steps, recomputed on
+    // even ones: both routes are checked
+    a.mom = (s & 1) ? auxs[s + 1].data() : nullptr;
+    if (!a.mom)
+      for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
     for (int c = 0; c < (int)nc; ++c) adj_collide_cell<C>(a, P, c, gpar.data());
     for (int c = 0; c < (int)nc; ++c) adj_gather_cell<C>(a, P, c, false, gpar.data());
     lpA.swap(lpB);
@@ -122,7 +128,9 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, d
   }
   a.pin = pops[0].data();
   a.ain = auxs[0].data();
+  a.mom = nullptr;
   a.lpin = lpA.data();
+  a.lain = laA.data();
   for (int c = 0; c < (int)nc; ++c) adj_init_latent_cell<C>(a, P, c, gpar.data());
   for (int k = 0; k < NPAR; ++k) grad[k] = gpar[k];
   return 0;

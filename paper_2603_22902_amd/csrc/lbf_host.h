@@ -188,9 +188,11 @@ inline AdjBufLayout make_adj_layout(const lbf_params* P, const Layout& F) {
     A.off_lp[k] = o;
     o = align256(o + F.pop_bytes);
   }
+  // adjoint of the lagged fields plus N + 1 per-cell population scalars
+  const size_t la_bytes = F.aux_bytes + (size_t)(P->nphase + 1) * ncell * F.elt;
   for (int k = 0; k < 2; ++k) {
     A.off_la[k] = o;
-    o = align256(o + F.aux_bytes);
+    o = align256(o + la_bytes);
   }
   A.off_work = o;
   o = align256(o + (size_t)A.nwork * ncell * relt);

@@ -24,8 +24,8 @@ struct Ops {
   // Passes of the reverse step (lbf_adjoint_kernels.h); NULL where the
   // adjoint is not built (3D, float32 storage with float64 arithmetic).
   hipError_t (*adjoint)(int pass, const void* pin, const void* ain, const void* lpin, const void* lain,
-                        void* lpout, void* laout, void* work, const KParams& P, const KParams* dP,
-                        double* part, double A, double B, hipStream_t s);
+                        void* lpout, void* laout, const void* mom, void* work, const KParams& P,
+                        const KParams* dP, double* part, double A, double B, hipStream_t s);
 };
 
 // dim 2 or 3, nphase 1..4; NULL if not built.  f32: float32 storage and
@@ -69,14 +69,15 @@ const Ops* ops_mix(int dim, int nphase);
       return launch_widen<ST>(static_cast<const ST*>(in), out, n, s);                            \
     }                                                                                            \
     static hipError_t adjoint(int pass, const void* pin, const void* ain, const void* lpin,     \
-                              const void* lain, void* lpout, void* laout, void* work,            \
+                              const void* lain, void* lpout, void* laout, const void* mom,       \
+                              void* work,                                                        \
                               const KParams& P, const KParams* dP, double* part, double A,       \
                               double B, hipStream_t s) {                                         \
       if constexpr (ADJ && DIM == 2)                                                             \
         return launch_adjoint<DIM, NP, ST, RT>(                                                  \
             pass, static_cast<const ST*>(pin), static_cast<const ST*>(ain),                      \
             static_cast<const ST*>(lpin), static_cast<const ST*>(lain), static_cast<ST*>(lpout), \
-            static_cast<ST*>(laout), work, P, dP, part, A, B, s);                                \
+            static_cast<ST*>(laout), static_cast<const ST*>(mom), work, P, dP, part, A, B, s);   \
       else                                                                                       \
         return hipErrorNotSupported;                                                             \
     }                                                                                            \

@@ -71,7 +71,7 @@ def lib():
         L.lbf_adjoint_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_adjoint_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.lbf_adjoint_seed.argtypes = [vp, _PD]
-        L.lbf_adjoint_step.argtypes = [vp, vp]
+        L.lbf_adjoint_step.argtypes = [vp, vp, vp]
         L.lbf_adjoint_finish.argtypes = [vp, vp]
         L.lbf_adjoint_gradient.argtypes = [vp, _PD]
         L.lbf_adjoint_state.argtypes = [vp, _PD, _PD]
