@@ -229,6 +229,39 @@ lbf_status lbf_adjoint_state(lbf_adj* adj, double* pops, double* aux);
 /* Release the adjoint context (not its buffer).  NULL is a no-op. */
 lbf_status lbf_adjoint_destroy(lbf_adj* adj);
 
+/* ---- Batched cases ---------------------------------------------------------
+ * Many independent 2D cases (any grid sizes, parameters and phase counts;
+ * one precision, one device) advance together: per time step, one moments
+ * launch and one collide launch over all cases of each phase count N.  Each
+ * case's result is bitwise that of lbf_step on its own context.  A batch
+ * needs a non-default HIP stream (it is captured into a graph); it orders its
+ * launches after nothing else, so the caller synchronises the members'
+ * streams before batch calls.  Members must not be stepped on their own while
+ * in the batch (LBF_ESTATE); lbf_batch_step and lbf_batch_replay update their
+ * states and step counts.  The caller allocates lbf_batch_bytes of device
+ * memory (256-byte aligned, case tables) for the batch's lifetime. */
+typedef struct lbf_batch lbf_batch;
+lbf_status lbf_batch_bytes(lbf_ctx* const* ctxs, int n, size_t* bytes);
+lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t bytes, void* hip_stream,
+                            lbf_batch** out);
+/* Row tile per phase count: tile[N-1] in {64, 128, 256}, 0 keeps the current
+ * one (the default is 128). */
+lbf_status lbf_batch_set_tiles(lbf_batch* b, const int* tile);
+/* Autotuner: for each phase count, time trial_steps passes with each row tile
+ * (passes that read the current states and write only the scratch buffers,
+ * so the states do not change) and keep the fastest; tile[4] receives the
+ * choice (0 where the batch has no case of that N); tile may be NULL. */
+lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile);
+/* nsteps batched steps, launched one by one (asynchronous on the batch's
+ * stream). */
+lbf_status lbf_batch_step(lbf_batch* b, int nsteps);
+/* Capture two batched steps into a HIP graph (replacing a previous one);
+ * lbf_batch_replay launches it times times (2 * times steps). */
+lbf_status lbf_batch_capture(lbf_batch* b);
+lbf_status lbf_batch_replay(lbf_batch* b, int times);
+/* Release the batch (not the contexts or the buffer).  NULL is a no-op. */
+lbf_status lbf_batch_destroy(lbf_batch* b);
+
 /* Steps taken since lbf_init_fields (restored by lbf_load_state). */
 lbf_status lbf_step_count(const lbf_ctx* ctx, long long* steps);
 

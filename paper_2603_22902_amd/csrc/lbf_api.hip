@@ -6,9 +6,11 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lbfreeze.h"
 #include "lbf_adjoint.h"
+#include "lbf_batch.h"
 #include "lbf_host.h"
 #include "lbf_ops.h"
 
@@ -26,6 +28,28 @@ struct lbf_ctx {
   bool initialized, nan_flag;
   long long steps;
   std::string err;
+};
+
+// A batch: the member contexts grouped by phase count; each group's case
+// table (BatchCase, storage-type independent layout) lives in the caller's
+// device buffer.
+struct lbf_batch_group {
+  std::vector<lbf_ctx*> ctx;
+  std::vector<int> cur0;  // buffer of each case at even batch steps
+  int variant;            // row tile BATCH_TILES[variant]
+  int cblocks, mblocks;   // grid sizes of the two passes
+  size_t off;             // case table offset in the device buffer
+};
+
+struct lbf_batch {
+  lbf_ctx* first;
+  lbf_batch_group g[lbf::MAXP];
+  char* base;
+  hipStream_t stream;
+  int parity;  // batch steps taken mod 2
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int graph_parity;
 };
 
 struct lbf_adj {
@@ -165,6 +189,7 @@ lbf_status lbf_create(const lbf_params* prm, void* dev_buf, size_t bytes, void* 
   c->ncell = c->kp.ncell;
   c->base = static_cast<char*>(dev_buf);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
   c->cur = 0;
   c->initialized = c->nan_flag = false;
   c->steps = 0;
@@ -624,6 +649,318 @@ lbf_status lbf_adjoint_state(lbf_adj* a, double* pops, double* aux) {
 
 lbf_status lbf_adjoint_destroy(lbf_adj* a) {
   delete a;
+  return LBF_OK;
+}
+
+}  // extern "C"
+
+// ----- batched cases ---------------------------------------------------
+namespace {
+
+size_t batch_table_bytes(int n) { return lbf::align256((size_t)n * sizeof(lbf::BatchCase<float>)); }
+
+lbf_status batch_validate(lbf_ctx* const* ctxs, int n, std::string& err) {
+  if (!ctxs || n < 1) {
+    err = "no contexts";
+    return LBF_EINVAL;
+  }
+  for (int k = 0; k < n; ++k) {
+    lbf_ctx* c = ctxs[k];
+    if (!c) {
+      err = "NULL context";
+      return LBF_EINVAL;
+    }
+    if (!c->ops->batch) {
+      err = "batched steps are built for 2D";
+      return LBF_ENOTSUP;
+    }
+    if (c->prm.precision != ctxs[0]->prm.precision || c->device != ctxs[0]->device) {
+      err = "contexts of a batch share the precision and the device";
+      return LBF_EINVAL;
+    }
+    if (!c->initialized) {
+      err = "lbf_init_fields has not been called on every context";
+      return LBF_ESTATE;
+    }
+    for (int j = 0; j < k; ++j)
+      if (ctxs[j] == c) {
+        err = "a context appears twice";
+        return LBF_EINVAL;
+      }
+  }
+  return LBF_OK;
+}
+
+// Case table of group g for row tile variant v: geometry per case (about
+// 4096 collide blocks over the group, split by cell counts), block offsets.
+template <typename S>
+void batch_table(const lbf_batch_group& g, int v, std::vector<lbf::BatchCase<S>>& t, int& cblocks, int& mblocks) {
+  long long total = 0;
+  for (lbf_ctx* c : g.ctx) total += c->ncell;
+  t.resize(g.ctx.size());
+  cblocks = mblocks = 0;
+  for (size_t k = 0; k < g.ctx.size(); ++k) {
+    lbf_ctx* c = g.ctx[k];
+    lbf::BatchCase<S>& b = t[k];
+    b.P = kp_ptr(c);
+    for (int j = 0; j < 2; ++j) {
+      b.pop[j] = static_cast<S*>(pop_ptr(c, j));
+      b.aux[j] = static_cast<S*>(aux_ptr(c, j));
+    }
+    b.cur = g.cur0[k];
+    const long long target = (4096LL * c->ncell + total - 1) / total;
+    lbf::batch_geometry(c->kp, lbf::BATCH_TILES[v], target, b.ntx, b.chunk, b.nblocks);
+    b.nty = 1;
+    b.mblocks = (int)((c->ncell + lbf::MOMENT_THREADS - 1) / lbf::MOMENT_THREADS);
+    b.first_cblock = cblocks;
+    b.first_mblock = mblocks;
+    cblocks += b.nblocks;
+    mblocks += b.mblocks;
+  }
+}
+
+lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
+  lbf_batch_group& g = b->g[gi];
+  lbf_ctx* c0 = b->first;
+  void* dst = b->base + g.off;
+  if (c0->prm.precision == LBF_FP64) {
+    std::vector<lbf::BatchCase<double>> t;
+    batch_table<double>(g, v, t, g.cblocks, g.mblocks);
+    HIPCHK(c0, hipMemcpyAsync(dst, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
+           "hipMemcpyAsync");
+    HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  } else {
+    std::vector<lbf::BatchCase<float>> t;
+    batch_table<float>(g, v, t, g.cblocks, g.mblocks);
+    HIPCHK(c0, hipMemcpyAsync(dst, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
+           "hipMemcpyAsync");
+    HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  }
+  g.variant = v;
+  return LBF_OK;
+}
+
+// One batched step of every group at the given parity (the state buffers
+// read are cur0 ^ parity).
+lbf_status batch_launch(lbf_batch* b, int parity) {
+  lbf_ctx* c0 = b->first;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    if (g.ctx.empty()) continue;
+    const lbf::Ops* ops = g.ctx[0]->ops;
+    const int n = (int)g.ctx.size();
+    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, b->stream), "batched moments");
+    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, b->stream), "batched collide");
+  }
+  return LBF_OK;
+}
+
+lbf_status batch_check_members(lbf_batch* b) {
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    for (size_t k = 0; k < g.ctx.size(); ++k)
+      if (g.ctx[k]->cur != (g.cur0[k] ^ b->parity))
+        return fail(b->first, LBF_ESTATE, "a member context was stepped outside the batch");
+  }
+  return LBF_OK;
+}
+
+void batch_advance(lbf_batch* b, int nsteps) {
+  b->parity ^= (nsteps & 1);
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    for (size_t k = 0; k < g.ctx.size(); ++k) {
+      g.ctx[k]->cur = g.cur0[k] ^ b->parity;
+      g.ctx[k]->steps += nsteps;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lbf_status lbf_batch_bytes(lbf_ctx* const* ctxs, int n, size_t* bytes) {
+  if (!bytes) return LBF_EINVAL;
+  std::string err;
+  const lbf_status st = batch_validate(ctxs, n, err);
+  if (st != LBF_OK) return st;
+  int cnt[lbf::MAXP] = {0, 0, 0, 0};
+  for (int k = 0; k < n; ++k) ++cnt[ctxs[k]->N - 1];
+  size_t o = 0;
+  for (int gi = 0; gi < lbf::MAXP; ++gi)
+    if (cnt[gi]) o += batch_table_bytes(cnt[gi]);
+  *bytes = o;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t bytes, void* hip_stream,
+                            lbf_batch** out) {
+  if (!out) return LBF_EINVAL;
+  *out = nullptr;
+  std::string err;
+  const lbf_status st = batch_validate(ctxs, n, err);
+  if (st != LBF_OK) {
+    if (ctxs && n > 0 && ctxs[0]) fail(ctxs[0], st, err);
+    return st;
+  }
+  size_t need;
+  lbf_batch_bytes(ctxs, n, &need);
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255) || bytes < need)
+    return fail(ctxs[0], LBF_EINVAL, "batch buffer missing, unaligned or smaller than lbf_batch_bytes");
+  if (!hip_stream) return fail(ctxs[0], LBF_EINVAL, "a batch needs a non-default stream (graph capture)");
+  lbf_batch* b = new (std::nothrow) lbf_batch();
+  if (!b) return LBF_ENOMEM;
+  b->first = ctxs[0];
+  b->base = static_cast<char*>(dev_buf);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->parity = 0;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->graph_parity = 0;
+  for (int k = 0; k < n; ++k) {
+    lbf_batch_group& g = b->g[ctxs[k]->N - 1];
+    g.ctx.push_back(ctxs[k]);
+    g.cur0.push_back(ctxs[k]->cur);
+  }
+  size_t o = 0;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    if (g.ctx.empty()) continue;
+    g.off = o;
+    o += batch_table_bytes((int)g.ctx.size());
+    const lbf_status s2 = batch_set_variant(b, gi, 1);
+    if (s2 != LBF_OK) {
+      delete b;
+      return s2;
+    }
+  }
+  *out = b;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_set_tiles(lbf_batch* b, const int* tile) {
+  if (!b || !tile) return LBF_EINVAL;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    if (b->g[gi].ctx.empty() || tile[gi] == 0) continue;
+    int v = -1;
+    for (int k = 0; k < 3; ++k)
+      if (lbf::BATCH_TILES[k] == tile[gi]) v = k;
+    if (v < 0) return fail(b->first, LBF_EINVAL, "row tile must be 64, 128 or 256");
+    ADJCHK(batch_set_variant(b, gi, v));
+  }
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile) {
+  if (!b) return LBF_EINVAL;
+  if (trial_steps < 1) return fail(b->first, LBF_EINVAL, "trial_steps must be >= 1");
+  lbf_ctx* c0 = b->first;
+  ADJCHK(batch_check_members(b));
+  hipEvent_t e0, e1;
+  HIPCHK(c0, hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c0, LBF_EDEVICE, "hipEventCreate");
+  }
+  lbf_status result = LBF_OK;
+  for (int gi = 0; gi < lbf::MAXP && result == LBF_OK; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    if (tile) tile[gi] = 0;
+    if (g.ctx.empty()) continue;
+    const lbf::Ops* ops = g.ctx[0]->ops;
+    const int n = (int)g.ctx.size();
+    float best = 0.f;
+    int bestv = 1;
+    for (int v = 0; v < 3 && result == LBF_OK; ++v) {
+      result = batch_set_variant(b, gi, v);
+      if (result != LBF_OK) break;
+      // Trial passes read the current state and write only the scratch
+      // buffers (the parity is not advanced): the state is unchanged.
+      float ms = 0.f;
+      hipError_t e = hipSuccess;
+      for (int rep = 0; rep <= trial_steps && e == hipSuccess; ++rep) {
+        if (rep == 1) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, b->stream);
+        if (e == hipSuccess) e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, b->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        result = hip_fail(c0, e, "batch autotune");
+        break;
+      }
+      if (v == 0 || ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    if (result == LBF_OK) result = batch_set_variant(b, gi, bestv);
+    if (tile) tile[gi] = lbf::BATCH_TILES[bestv];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
+lbf_status lbf_batch_step(lbf_batch* b, int nsteps) {
+  if (!b) return LBF_EINVAL;
+  if (nsteps < 0) return fail(b->first, LBF_EINVAL, "nsteps must be >= 0");
+  ADJCHK(batch_check_members(b));
+  for (int s = 0; s < nsteps; ++s) {
+    ADJCHK(batch_launch(b, b->parity));
+    batch_advance(b, 1);
+  }
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_capture(lbf_batch* b) {
+  if (!b) return LBF_EINVAL;
+  lbf_ctx* c0 = b->first;
+  ADJCHK(batch_check_members(b));
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  HIPCHK(c0, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  lbf_status st = batch_launch(b, b->parity);
+  if (st == LBF_OK) st = batch_launch(b, b->parity ^ 1);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+  if (st != LBF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  HIPCHK(c0, e, "hipStreamEndCapture");
+  b->graph = graph;
+  HIPCHK(c0, hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  b->graph_parity = b->parity;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_replay(lbf_batch* b, int times) {
+  if (!b) return LBF_EINVAL;
+  lbf_ctx* c0 = b->first;
+  if (!b->exec) return fail(c0, LBF_ESTATE, "lbf_batch_capture has not been called");
+  if (times < 0) return fail(c0, LBF_EINVAL, "times must be >= 0");
+  if (b->parity != b->graph_parity)
+    return fail(c0, LBF_ESTATE, "an odd number of eager batch steps since the capture");
+  ADJCHK(batch_check_members(b));
+  for (int k = 0; k < times; ++k) HIPCHK(c0, hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+  batch_advance(b, 2 * times);
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_destroy(lbf_batch* b) {
+  if (!b) return LBF_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
   return LBF_OK;
 }
 

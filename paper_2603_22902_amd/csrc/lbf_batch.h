@@ -1,0 +1,156 @@
+// Batched time step: many independent cases (different grid sizes and
+// parameters, one phase count N) advance together, each pass one launch over
+// all cases.  A block looks up its case in the case table (binary search over
+// the cases' first block numbers), copies the case's parameter block into LDS
+// and runs the same phase functions as the single-case kernels.  The result
+// of each case is bitwise that of its single-case step: the per-cell
+// arithmetic does not depend on the tile shape or on the batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbf_kernels.h"
+
+namespace lbf {
+
+// One case of a batch.  Buffer cur holds the state at even batch steps.
+template <typename S>
+struct BatchCase {
+  const KParams* P;  // device copy of the case's parameter block
+  S* pop[2];
+  S* aux[2];
+  int cur;
+  int ntx, nty, chunk, nblocks;  // collide-pass geometry of this case
+  int mblocks;                   // moments-pass blocks of this case
+  int first_cblock, first_mblock;
+};
+
+// Last case k with first[k] <= b (uniform across the block).
+template <typename S>
+__device__ inline int batch_case(const BatchCase<S>* cs, int ncase, int b, bool collide) {
+  int lo = 0, hi = ncase - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int f = collide ? cs[mid].first_cblock : cs[mid].first_mblock;
+    if (f <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline void load_params(KParams& dst, const KParams* src) {
+  static_assert(sizeof(KParams) % 4 == 0, "parameter block is copied as 32-bit words");
+  const int* s = reinterpret_cast<const int*>(src);
+  int* d = reinterpret_cast<int*>(&dst);
+  for (int k = threadIdx.x; k < (int)(sizeof(KParams) / 4); k += blockDim.x) d[k] = s[k];
+  __syncthreads();
+}
+
+template <class C>
+__global__ void __launch_bounds__(MOMENT_THREADS)
+    batch_moment_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int parity) {
+  using S = typename C::S;
+  __shared__ KParams P;
+  const int k = batch_case<S>(cs, ncase, blockIdx.x, false);
+  const BatchCase<S>& bc = cs[k];
+  load_params(P, bc.P);
+  const int in = bc.cur ^ parity;
+  StepArgs<S> a;
+  a.pin = bc.pop[in];
+  a.ain = bc.aux[in];
+  a.aout = bc.aux[1 - in];
+  const int cell = (blockIdx.x - bc.first_mblock) * MOMENT_THREADS + threadIdx.x;
+  if (cell < P.ncell) moment_cell<C>(a, P, cell);
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::NT)
+    batch_collide_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nblocks, int parity) {
+  using S = typename C::S;
+  __shared__ KParams P;
+  __shared__ Smem<C> sm;
+  const int Lg = xcd_remap(blockIdx.x, nblocks);
+  const int k = batch_case<S>(cs, ncase, Lg, true);
+  const BatchCase<S>& bc = cs[k];
+  load_params(P, bc.P);
+  const int in = bc.cur ^ parity;
+  StepArgs<S> a;
+  a.pin = bc.pop[in];
+  a.pout = bc.pop[1 - in];
+  a.ain = bc.aux[in];
+  a.aout = bc.aux[1 - in];
+  a.mom = a.aout;
+  a.mout = nullptr;
+  a.mfield = 0;
+  a.ntx = bc.ntx;
+  a.nty = bc.nty;
+  a.chunk = bc.chunk;
+  a.nblocks = bc.nblocks;
+  const BlockPos bp = block_pos_local<C>(a, P, Lg - bc.first_cblock);
+  const int tid = threadIdx.x;
+  if (bp.w0 == 0) {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, 0);
+    __syncthreads();
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, -1);
+  } else {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
+  }
+  __syncthreads();
+  for (int w = bp.w0; w < bp.w1; ++w) {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
+    __syncthreads();
+    if (w == 0 || w == P.nwn - 1)
+      process_cell<C, false, true>(a, P, sm, bp, tid, w);
+    else
+      process_cell<C, false, false>(a, P, sm, bp, tid, w);
+    __syncthreads();
+  }
+}
+
+// 2D row tiles the batch can use (the autotuner picks one per phase count).
+constexpr int BATCH_TILES[3] = {64, 128, 256};
+
+// Geometry of one case for a row tile of tx cells: ntx tiles per row and a
+// chunk of layers chosen so that the case gets about `target` blocks (at
+// least two layers per chunk).
+inline void batch_geometry(const KParams& P, int tx, long long target, int& ntx, int& chunk, int& nblocks) {
+  ntx = (P.nx + tx - 1) / tx;
+  long long c = ((long long)P.nwn * ntx + target - 1) / (target > 0 ? target : 1);
+  if (c < 2) c = 2;
+  if (c > P.nwn) c = P.nwn;
+  chunk = (int)c;
+  nblocks = (int)((long long)ntx * ((P.nwn + chunk - 1) / chunk));
+}
+
+// pass 0: moments, 1: collide; variant indexes BATCH_TILES.
+template <int NP, typename S, typename R>
+inline hipError_t launch_batch(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
+                               hipStream_t s) {
+  const auto* cs = static_cast<const BatchCase<S>*>(cases);
+  if (pass == 0) {
+    hipLaunchKernelGGL((batch_moment_kernel<Cfg<2, NP, S, R, 128, 1>>), dim3(nblocks), dim3(MOMENT_THREADS), 0, s,
+                       cs, ncase, parity);
+    return hipGetLastError();
+  }
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 64, 1>>), dim3(nblocks), dim3(64), 0, s, cs, ncase,
+                         nblocks, parity);
+      break;
+    case 1:
+      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 128, 1>>), dim3(nblocks), dim3(128), 0, s, cs,
+                         ncase, nblocks, parity);
+      break;
+    case 2:
+      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 256, 1>>), dim3(nblocks), dim3(256), 0, s, cs,
+                         ncase, nblocks, parity);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbf

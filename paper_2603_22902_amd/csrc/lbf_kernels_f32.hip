@@ -2,6 +2,7 @@
 // float32; enthalpy inversion, rho H and the rest enthalpy population in
 // float64).
 #include "lbf_adjoint_kernels.h"
+#include "lbf_batch.h"
 #include "lbf_kernels.h"
 #include "lbf_ops.h"
 

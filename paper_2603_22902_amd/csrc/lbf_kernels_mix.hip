@@ -1,6 +1,7 @@
 // float32 storage with float64 arithmetic: the HBM traffic of the float32
 // path with the rounding of float64 arithmetic inside each step.
 #include "lbf_adjoint_kernels.h"
+#include "lbf_batch.h"
 #include "lbf_kernels.h"
 #include "lbf_ops.h"
 

@@ -26,6 +26,10 @@ struct Ops {
   hipError_t (*adjoint)(int pass, const void* pin, const void* ain, const void* lpin, const void* lain,
                         void* lpout, void* laout, const void* mom, void* work, const KParams& P,
                         const KParams* dP, double* part, double A, double B, hipStream_t s);
+  // Batched passes over a case table (lbf_batch.h), 2D only (NULL in 3D):
+  // pass 0 moments, 1 collide with row tile BATCH_TILES[variant].
+  hipError_t (*batch)(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
+                      hipStream_t s);
 };
 
 // dim 2 or 3, nphase 1..4; NULL if not built.  f32: float32 storage and
@@ -81,8 +85,16 @@ const Ops* ops_mix(int dim, int nphase);
       else                                                                                       \
         return hipErrorNotSupported;                                                             \
     }                                                                                            \
+    static hipError_t batch(int pass, int variant, const void* cases, int ncase, int nblocks,    \
+                            int parity, hipStream_t s) {                                         \
+      if constexpr (DIM == 2)                                                                    \
+        return launch_batch<NP, ST, RT>(pass, variant, cases, ncase, nblocks, parity, s);        \
+      else                                                                                       \
+        return hipErrorNotSupported;                                                             \
+    }                                                                                            \
     static constexpr Ops ops = {&step, &init, &diag, &widen,                                     \
-                                (ADJ && DIM == 2) ? &adjoint : nullptr};                         \
+                                (ADJ && DIM == 2) ? &adjoint : nullptr,                          \
+                                DIM == 2 ? &batch : nullptr};                                    \
   };                                                                                             \
   const Ops* NAME(int dim, int nphase) {                                                         \
     static const Ops* table[2][4] = {                                                            \

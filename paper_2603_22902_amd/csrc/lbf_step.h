@@ -111,10 +111,10 @@ __host__ __device__ inline int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// Tile and layer chunk of logical block Lg of one grid.
 template <class C>
-__host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, const KParams& P,
-                                              int b) {
-  const int Lg = xcd_remap(b, a.nblocks);
+__host__ __device__ inline BlockPos block_pos_local(const StepArgs<typename C::S>& a, const KParams& P,
+                                                    int Lg) {
   const int ntiles = a.ntx * a.nty;
   const int chunk_id = Lg / ntiles, tile = Lg % ntiles;
   BlockPos bp;
@@ -124,6 +124,12 @@ __host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, 
   const int w1 = bp.w0 + a.chunk;
   bp.w1 = w1 < P.nwn ? w1 : P.nwn;
   return bp;
+}
+
+template <class C>
+__host__ __device__ inline BlockPos block_pos(const StepArgs<typename C::S>& a, const KParams& P,
+                                              int b) {
+  return block_pos_local<C>(a, P, xcd_remap(b, a.nblocks));
 }
 
 // Mixture law, eq. (eq2).

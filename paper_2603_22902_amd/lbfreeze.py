@@ -76,6 +76,15 @@ def lib():
         L.lbf_adjoint_gradient.argtypes = [vp, _PD]
         L.lbf_adjoint_state.argtypes = [vp, _PD, _PD]
         L.lbf_adjoint_destroy.argtypes = [vp]
+        L.lbf_batch_bytes.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_size_t, vp,
+                                       ctypes.POINTER(vp)]
+        L.lbf_batch_set_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.lbf_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.lbf_batch_step.argtypes = [vp, ctypes.c_int]
+        L.lbf_batch_capture.argtypes = [vp]
+        L.lbf_batch_replay.argtypes = [vp, ctypes.c_int]
+        L.lbf_batch_destroy.argtypes = [vp]
         L.lbf_get_moments.argtypes = [vp, ctypes.c_uint, _PD]
         L.lbf_get_populations.argtypes = [vp, _PD]
         L.lbf_get_aux.argtypes = [vp, _PD]
@@ -95,7 +104,9 @@ def lib():
                      "lbf_step_count", "lbf_destroy", "lbf_state_device_bytes",
                      "lbf_state_to_device", "lbf_state_from_device", "lbf_step_states", "lbf_adjoint_bytes",
                      "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_step", "lbf_adjoint_finish",
-                     "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy"):
+                     "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy",
+                     "lbf_batch_bytes", "lbf_batch_create", "lbf_batch_set_tiles", "lbf_batch_tune",
+                     "lbf_batch_step", "lbf_batch_capture", "lbf_batch_replay", "lbf_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

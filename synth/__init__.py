@@ -258,6 +258,43 @@ def small(dim=2, shape=(70, 37), nphase=2, precision="fp64", seed_k=11,
     return _case("small", prm, phi, T, steps)
 
 
+def batch(n_cases=64, seed_k=5, precision="fp32", sizes=(64, 128, 256, 512)):
+    """Independent 2D droplet-freezing cases for a batched run.  For each
+    case, in this order: the side L from sizes, the contact angle
+    theta ~ U[60, 120] deg, the Stefan number Ste ~ U[0.05, 0.2] and N from
+    {2, 3}.  A droplet of radius L/4 sits on the cold wall (with an
+    encapsulated core of radius L/8 for N = 3), gas elsewhere."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + seed_k))
+    out = []
+    for _ in range(n_cases):
+        L = int(rng.choice(sizes))
+        theta = float(rng.uniform(60.0, 120.0))
+        ste = float(rng.uniform(0.05, 0.2))
+        N = int(rng.choice([2, 3]))
+        c = math.cos(math.radians(theta))
+        if N == 2:
+            phases = [freezing_phase(ratio=0.9, lam=0.15, ste=ste), inert_phase(0.01, lam=0.225)]
+            ct = [[0.0, c], [-c, 0.0]]
+        else:
+            phases = [freezing_phase(ratio=1.1, lam=0.05, ste=ste),
+                      freezing_phase(ratio=0.9, lam=0.15, ste=ste), inert_phase(0.01, lam=0.075)]
+            ct = [[0.0, 0.0, 0.0], [0.0, 0.0, c], [0.0, -c, 0.0]]
+        prm = make_params(2, (L, L), phases, sigma=1e-3, precision=precision, cos_theta=ct)
+        x, y, z = grid(prm)
+        r = np.sqrt((x - L / 2) ** 2 + y ** 2)
+        drop = tanh_in(L / 4 - r)
+        if N == 2:
+            phi = np.stack([drop, 1.0 - drop])
+        else:
+            core = tanh_in(L / 8 - r)
+            phi = np.stack([drop * core, drop * (1.0 - core), 1.0 - drop])
+        T = np.full(drop.shape, T_HOT)
+        case = _case("batch", prm, phi, T, 200)
+        case.update(theta_deg=theta, ste=ste)
+        out.append(case)
+    return out
+
+
 def near_melting(case, T_wall=0.005, T_top=0.025):
     """The case with a liquid start just above the melting point, T rising
     linearly from T_wall at the cold wall to T_top at the far face, and no
