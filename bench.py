@@ -163,6 +163,55 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
             "J": J, "dJ_dTw": dJ_dTw, "dJ_dSte": dJ_dSte}
 
 
+def batch_leg(nsteps: int = 200, precision: str = "fp32") -> dict:
+    """The 64-case 2D sweep (sides 64..512, N 2 or 3): total-cells MLUPS of
+    (a) the batch replayed from its captured graph after autotuning, (b) the
+    same batch launched step by step, (c) the cases looped one by one with
+    their own launches; each from the same start, timed with events."""
+    import torch
+
+    import synth
+    from paper_2603_22902_amd import Solver
+    from paper_2603_22902_amd.batch import Batch
+
+    cases = synth.batch(n_cases=64, precision=precision)
+    solvers = []
+    for c in cases:
+        s = Solver(c["params"])
+        s.init_case(c)
+        solvers.append(s)
+    ncell = sum(s.ncell for s in solvers)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, stream):
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    # (c) looped single-case solves on the solvers' own stream
+    for s in solvers:
+        s.lbf_step(2)
+    t_loop = timed(lambda: [s.lbf_step(nsteps) for s in solvers], solvers[0].stream)
+    b = Batch(solvers)
+    tiles = b.tune(3)
+    b.step(2)
+    t_eager = timed(lambda: b.step(nsteps), b.stream)
+    b.capture()
+    b.replay(1)
+    t_graph = timed(lambda: b.replay(nsteps // 2), b.stream)
+    mlups = lambda ms: round(ncell * nsteps / (ms * 1e-3) / 1e6, 1)
+    out = {"workload": f"{len(cases)} 2D cases, sides 64..512, N 2 or 3, {ncell} cells",
+           "steps": nsteps, "precision": precision, "tiles": {str(k): v for k, v in tiles.items()},
+           "mlups_graph": mlups(t_graph), "mlups_batch_eager": mlups(t_eager),
+           "mlups_looped_single": mlups(t_loop),
+           "speedup_graph_vs_looped": round(t_loop / t_graph, 3)}
+    b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +221,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver's time step runs on one device; "
@@ -248,6 +298,9 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg()
         print(f"[bench] adjoint leg {out['adjoint']}", file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["batch"] = batch_leg()
+        print(f"[bench] batch leg {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
