@@ -842,10 +842,22 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
 // the inversion and the moments.  seed = true: the objective's adjoints of
 // phi, f_s stand in the own planes and every other input adjoint is zero
 // (the populations' adjoints are then written, not added to).
+// fda(k, xcell, dl0, dl1, dw) returns work plane k (an FD-adjoint plane) of
+// reader cell xcell, which sits at lateral offsets (dl0, dl1) and layer
+// offset dw from this cell: from global memory, or from an LDS tile.
 // ---------------------------------------------------------------------------
 template <class C>
+struct FdaGlobal {
+  const AdjArgs<C>* a;
+  long long nc;
+  __host__ __device__ typename C::R operator()(int k, int xcell, int, int, int) const {
+    return wplane(*a, k, nc)[xcell];
+  }
+};
+
+template <class C, class FDA>
 __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KParams& P, int cell, bool seed,
-                                                double* gpar) {
+                                                double* gpar, const FDA& fda) {
   using R = typename C::R;
   using ST = typename C::S;
   using Lt = typename C::L;
@@ -870,21 +882,22 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
 
     // Contribution of reader x (direction i reads this cell or its ghost
     // image) to the adjoints of the values read: phi, f_s, rho, u^{n-1}.
-    auto reader = [&](int xcell, int i, R* Ab, R& fsrb, R& rhorb, R* uprb, const R* phiread, R fsread) {
+    auto reader = [&](int xcell, int i, int dw, R* Ab, R& fsrb, R& rhorb, R* uprb, const R* phiread, R fsread) {
       const R wi = wgt<R, DIM>(i);
+      const int d0 = -Lt::cl0(i), d1 = -Lt::cl1(i);
       for (int p = 0; p < NP; ++p) {
         R g = R(0), gf = R(0);
         for (int d = 0; d < DIM; ++d) {
-          g += R(Lt::c(i, d)) * wplane(a, L::F_GPHI + p * DIM + d, nc)[xcell];
-          gf += R(Lt::c(i, d)) * wplane(a, L::F_GFP + p * DIM + d, nc)[xcell];
+          g += R(Lt::c(i, d)) * fda(L::F_GPHI + p * DIM + d, xcell, d0, d1, dw);
+          gf += R(Lt::c(i, d)) * fda(L::F_GFP + p * DIM + d, xcell, d0, d1, dw);
         }
-        Ab[p] += R(3) * wi * g + R(6) * wi * wplane(a, L::F_LPHI + p, nc)[xcell] + R(3) * wi * gf * fsread;
+        Ab[p] += R(3) * wi * g + R(6) * wi * fda(L::F_LPHI + p, xcell, d0, d1, dw) + R(3) * wi * gf * fsread;
         fsrb += R(3) * wi * gf * phiread[p];
       }
       R gr = R(0);
-      for (int d = 0; d < DIM; ++d) gr += R(Lt::c(i, d)) * wplane(a, L::F_GRHO + d, nc)[xcell];
+      for (int d = 0; d < DIM; ++d) gr += R(Lt::c(i, d)) * fda(L::F_GRHO + d, xcell, d0, d1, dw);
       rhorb += R(3) * wi * gr;
-      const R db = wplane(a, L::F_DIV, nc)[xcell];
+      const R db = fda(L::F_DIV, xcell, d0, d1, dw);
       for (int d = 0; d < DIM; ++d) uprb[d] += R(3) * wi * R(Lt::c(i, d)) * db;
     };
 
@@ -894,7 +907,7 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
       if (xw < 0 || xw >= P.nwn) continue;
       int xl = wrap1(gx - Lt::cl0(i), P.nx);
       if (DIM == 3) xl += wrap1(gy - Lt::cl1(i), P.ny) * P.nx;
-      reader(xw * area + xl, i, phib, fsb, rhob, upb, phi, fs);
+      reader(xw * area + xl, i, -Lt::cw(i), phib, fsb, rhob, upb, phi, fs);
     }
     // ghost images: a reader in the boundary layer whose direction leaves
     // through the face reads the ghost derived from this cell
@@ -920,7 +933,7 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
         if (Lt::cw(i) != (face == 0 ? -1 : 1)) continue;
         int xl = wrap1(gx - Lt::cl0(i), P.nx);
         if (DIM == 3) xl += wrap1(gy - Lt::cl1(i), P.ny) * P.nx;
-        reader(bw * area + xl, i, Ab, fsgb, rhogb, upgb, gval, fs);
+        reader(bw * area + xl, i, 0, Ab, fsgb, rhogb, upgb, gval, fs);
       }
       fsb += fsgb;
       rhob += rhogb;
@@ -973,6 +986,15 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
   for (int d = 0; d < DIM; ++d) plane(a.laout, C::A_U + d, nc)[cell] = ST(upb[d]);
   plane(a.laout, C::A_DIV, nc)[cell] = ST(Db);
   plane(a.laout, C::A_Q, nc)[cell] = ST(qb);
+}
+
+template <class C>
+__host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KParams& P, int cell, bool seed,
+                                                double* gpar) {
+  FdaGlobal<C> g;
+  g.a = &a;
+  g.nc = P.ncell;
+  adj_gather_cell<C>(a, P, cell, seed, gpar, g);
 }
 
 // Objective J = sum f_s psi / sum psi (frozen fraction of the freezing

@@ -84,6 +84,93 @@ __global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_e
   block_sum<NPAR, true>(g, part);
 }
 
+// The gather with the FD-adjoint planes of the tile and a one-cell halo
+// staged in an LDS ring of three layers, the block marching along the
+// wall-normal axis like the forward collide kernel (a non-seed pass).
+template <class C>
+struct FdaRing {
+  static constexpr int NF = AdjLayout<C>::F_DIV - AdjLayout<C>::F_GPHI + 1;
+  typename C::R v[3][NF][C::F];
+};
+
+template <class C>
+struct FdaLds {
+  const FdaRing<C>* ring;
+  int fc, w;
+  __host__ __device__ typename C::R operator()(int k, int, int dl0, int dl1, int dw) const {
+    return ring->v[slot(w + dw)][k - AdjLayout<C>::F_GPHI][fc + dl0 + dl1 * C::LX];
+  }
+};
+
+template <class C>
+__host__ __device__ inline void fda_fill(const AdjArgs<C>& a, const KParams& P, FdaRing<C>& r, const BlockPos& bp,
+                                         int f, int w) {
+  using L = AdjLayout<C>;
+  const int lx = f % C::LX, ly = f / C::LX;
+  int lat = wrapf(bp.tx0 + lx - 1, P.nx);
+  if (C::DIM == 3) lat += wrapf(bp.ty0 + ly - 1, P.ny) * P.nx;
+  const int cell = w * (int)P.area + lat;
+  const long long nc = P.ncell;
+#pragma unroll
+  for (int k = 0; k < FdaRing<C>::NF; ++k) r.v[slot(w)][k][f] = wplane(a, L::F_GPHI + k, nc)[cell];
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
+    adj_gather_tile_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part, int ntx,
+                           int nty, int chunk, int nblocks) {
+  const KParams& P = *kp;
+  __shared__ FdaRing<C> ring;
+  StepArgs<typename C::S> sa;
+  sa.ntx = ntx;
+  sa.nty = nty;
+  sa.chunk = chunk;
+  sa.nblocks = nblocks;
+  const BlockPos bp = block_pos<C>(sa, P, blockIdx.x);
+  const int tid = threadIdx.x;
+  const int tx = tid % C::TX, ty = tid / C::TX;
+  const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
+  const bool own = gx < P.nx && (C::DIM == 2 || gy < P.ny);
+  const int fc = (C::DIM == 3) ? (ty + 1) * C::LX + tx + 1 : tx + 1;
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  if (bp.w0 > 0)
+    for (int f = tid; f < C::F; f += C::NT) fda_fill<C>(a, P, ring, bp, f, bp.w0 - 1);
+  for (int f = tid; f < C::F; f += C::NT) fda_fill<C>(a, P, ring, bp, f, bp.w0);
+  __syncthreads();
+  for (int w = bp.w0; w < bp.w1; ++w) {
+    if (w + 1 < P.nwn)
+      for (int f = tid; f < C::F; f += C::NT) fda_fill<C>(a, P, ring, bp, f, w + 1);
+    __syncthreads();
+    if (own) {
+      FdaLds<C> acc;
+      acc.ring = &ring;
+      acc.fc = fc;
+      acc.w = w;
+      const int cell = w * (int)P.area + ((C::DIM == 3) ? gy * P.nx + gx : gx);
+      adj_gather_cell<C>(a, P, cell, false, g, acc);
+    }
+    __syncthreads();
+  }
+  // per-block parameter terms (fixed order, as block_sum)
+  __shared__ double red[C::NT / 64][NPAR];
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) {
+    double v = g[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][k] = v;
+  }
+  __syncthreads();
+  if (tid < NPAR) {
+    double t = 0.0;
+    for (int w = 0; w < C::NT / 64; ++w) t += red[w][tid];
+    part[(long long)blockIdx.x * NPAR + tid] += t;
+  }
+}
+
 template <class C>
 __global__ void __launch_bounds__(ADJ_THREADS)
     adj_objective_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
@@ -144,7 +231,15 @@ inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* 
   switch (pass) {
     case 0: hipLaunchKernelGGL((adj_moment_kernel<C>), grid, block, 0, s, a, dP); break;
     case 1: hipLaunchKernelGGL((adj_collide_kernel<C>), grid, block, 0, s, a, dP, part); break;
-    case 2: hipLaunchKernelGGL((adj_gather_kernel<C, false>), grid, block, 0, s, a, dP, part); break;
+    case 2: {
+      // the gradient rows of the buffer layout assume 128-cell rows and
+      // chunks of at least two layers in 2D
+      static_assert(DIM != 2 || (C::TX == 128 && C::TY == 1), "2D adjoint tile must be a 128-cell row");
+      const Geometry g = step_geometry<C>(P);
+      hipLaunchKernelGGL((adj_gather_tile_kernel<C>), dim3(g.nblocks), dim3(C::NT), 0, s, a, dP, part, g.ntx,
+                         g.nty, g.chunk, g.nblocks);
+      break;
+    }
     case 3: hipLaunchKernelGGL((adj_gather_kernel<C, true>), grid, block, 0, s, a, dP, part); break;
     case 4: hipLaunchKernelGGL((adj_objective_kernel<C>), grid, block, 0, s, a, dP, part); break;
     case 5: hipLaunchKernelGGL((adj_seed_kernel<C>), grid, block, 0, s, a, dP, A, B); break;

@@ -544,9 +544,9 @@ lbf_status adj_pass(lbf_adj* a, int pass, const void* pin, const void* ain, cons
   return LBF_OK;
 }
 
-lbf_status adj_reduce(lbf_adj* a, const double* part, int nv, double* out) {
+lbf_status adj_reduce(lbf_adj* a, const double* part, int nv, int nrows, double* out) {
   lbf_ctx* c = a->c;
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nv), dim3(256), 0, c->stream, part, a->lay.nblocks, nv, out);
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nv), dim3(256), 0, c->stream, part, nrows, nv, out);
   HIPCHK(c, hipGetLastError(), "adjoint reduction");
   return LBF_OK;
 }
@@ -566,7 +566,7 @@ lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) {
   const void* ain = aux_ptr(c, c->cur);
   ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
   ADJCHK(adj_pass(a, 4, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
-  ADJCHK(adj_reduce(a, adj_opart(a), 2, adj_obj(a)));
+  ADJCHK(adj_reduce(a, adj_opart(a), 2, a->lay.cblocks, adj_obj(a)));
   double AB[2];
   HIPCHK(c, hipMemcpyAsync(AB, adj_obj(a), sizeof AB, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -615,7 +615,7 @@ lbf_status lbf_adjoint_gradient(lbf_adj* a, double* grad) {
   lbf_ctx* c = a->c;
   if (!grad) return fail(c, LBF_EINVAL, "grad is NULL");
   if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
-  ADJCHK(adj_reduce(a, adj_part(a), lbf::NPAR, adj_acc(a)));
+  ADJCHK(adj_reduce(a, adj_part(a), lbf::NPAR, a->lay.nblocks, adj_acc(a)));
   HIPCHK(c, hipMemcpyAsync(grad, adj_acc(a), lbf::NPAR * sizeof(double), hipMemcpyDeviceToHost, c->stream),
          "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");

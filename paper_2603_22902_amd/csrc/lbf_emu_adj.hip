@@ -10,6 +10,7 @@
 
 #include "../../include/lbfreeze.h"
 #include "lbf_adjoint.h"
+#include "lbf_adjoint_kernels.h"
 #include "lbf_host.h"
 #include "lbf_kernels.h"
 
@@ -72,6 +73,43 @@ void objective(const AdjArgs<C>& a, const KParams& P, double& A, double& B) {
   }
 }
 
+// The tiled gather of adj_gather_tile_kernel, block by block, each barrier
+// phase for all threads before the next.
+template <class C>
+void gather_tiled(const AdjArgs<C>& a, const KParams& P, double* gpar) {
+  const Geometry g = step_geometry<C>(P);
+  StepArgs<typename C::S> sa;
+  memset(&sa, 0, sizeof sa);
+  sa.ntx = g.ntx;
+  sa.nty = g.nty;
+  sa.chunk = g.chunk;
+  sa.nblocks = g.nblocks;
+  std::vector<FdaRing<C>> rv(1);
+  FdaRing<C>& ring = rv[0];
+  for (int b = 0; b < g.nblocks; ++b) {
+    memset(&ring, 0xff, sizeof ring);  // poison: a read of an unfilled slot shows up as NaN
+    const BlockPos bp = block_pos<C>(sa, P, b);
+    if (bp.w0 > 0)
+      for (int f = 0; f < C::F; ++f) fda_fill<C>(a, P, ring, bp, f, bp.w0 - 1);
+    for (int f = 0; f < C::F; ++f) fda_fill<C>(a, P, ring, bp, f, bp.w0);
+    for (int w = bp.w0; w < bp.w1; ++w) {
+      if (w + 1 < P.nwn)
+        for (int f = 0; f < C::F; ++f) fda_fill<C>(a, P, ring, bp, f, w + 1);
+      for (int t = 0; t < C::NT; ++t) {
+        const int tx = t % C::TX, ty = t / C::TX;
+        const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
+        if (gx >= P.nx || (C::DIM == 3 && gy >= P.ny)) continue;
+        FdaLds<C> acc;
+        acc.ring = &ring;
+        acc.fc = (C::DIM == 3) ? (ty + 1) * C::LX + tx + 1 : tx + 1;
+        acc.w = w;
+        const int cell = w * (int)P.area + ((C::DIM == 3) ? gy * P.nx + gx : gx);
+        adj_gather_cell<C>(a, P, cell, false, gpar, acc);
+      }
+    }
+  }
+}
+
 template <int DIM, int NP, typename S, typename R>
 int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, double* J, double* grad) {
   using C = CfgOf<DIM, NP, S, R>;
@@ -122,7 +160,12 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, d
     if (!a.mom)
       for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
     for (int c = 0; c < (int)nc; ++c) adj_collide_cell<C>(a, P, c, gpar.data());
-    for (int c = 0; c < (int)nc; ++c) adj_gather_cell<C>(a, P, c, false, gpar.data());
+    // the tiled gather of the GPU kernel on every third step, the plain one
+    // otherwise: both are checked
+    if (s % 3 == 2)
+      gather_tiled<C>(a, P, gpar.data());
+    else
+      for (int c = 0; c < (int)nc; ++c) adj_gather_cell<C>(a, P, c, false, gpar.data());
     lpA.swap(lpB);
     laA.swap(laB);
   }

@@ -172,7 +172,9 @@ inline Layout make_layout(const lbf_params* P) {
 // the objective sums.
 struct AdjBufLayout {
   size_t off_lp[2], off_la[2], off_work, off_part, off_acc, off_obj, total;
-  int nblocks, nwork;
+  int nblocks;  // rows of the gradient accumulator: covers every adjoint grid
+  int cblocks;  // blocks of the one-thread-per-cell passes (256 cells each)
+  int nwork;
 };
 
 inline int adj_nwork(int N, int D) { return 2 * N * D + 4 * N + 2 * D + 6; }
@@ -181,7 +183,12 @@ inline AdjBufLayout make_adj_layout(const lbf_params* P, const Layout& F) {
   AdjBufLayout A;
   const long long ncell = (long long)P->nx * P->ny * (P->dim == 3 ? P->nz : 1);
   const size_t relt = P->precision == LBF_FP32 ? 4 : 8;
-  A.nblocks = (int)((ncell + 255) / 256);
+  A.cblocks = (int)((ncell + 255) / 256);
+  // The tiled gather's grid: 128-cell rows and chunks of at least two
+  // layers (2D), at most ceil(nx / 128) * ceil(nwn / 2) blocks.
+  const long long nwn = P->dim == 3 ? P->nz : P->ny;
+  const long long tiles = ((long long)(P->nx + 127) / 128) * ((nwn + 1) / 2);
+  A.nblocks = (int)(tiles > A.cblocks ? tiles : A.cblocks);
   A.nwork = adj_nwork(P->nphase, P->dim);
   size_t o = 0;
   for (int k = 0; k < 2; ++k) {
@@ -197,7 +204,7 @@ inline AdjBufLayout make_adj_layout(const lbf_params* P, const Layout& F) {
   A.off_work = o;
   o = align256(o + (size_t)A.nwork * ncell * relt);
   A.off_part = o;
-  o = align256(o + (size_t)A.nblocks * (22 + 2) * 8);
+  o = align256(o + (size_t)A.nblocks * 22 * 8 + (size_t)A.cblocks * 2 * 8);
   A.off_acc = o;
   o = align256(o + 22 * 8);
   A.off_obj = o;
