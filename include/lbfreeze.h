@@ -208,9 +208,21 @@ lbf_status lbf_step_states(lbf_ctx* ctx, const void* src, void* dst);
 typedef struct lbf_adj lbf_adj;
 lbf_status lbf_adjoint_bytes(const lbf_params* prm, size_t* bytes);
 lbf_status lbf_adjoint_create(lbf_ctx* ctx, void* dev_buf, size_t bytes, lbf_adj** out);
-/* Objective of the context's current state into *J (may be NULL); resets
- * the gradient and sets the adjoint state to dJ/dx^K.  LBF_EINVAL if the
- * state holds no freezing material. */
+/* Objectives of the final state x^K (psi = the freezing phases' fraction,
+ * f_s the solid fraction of eq. (H)'s inversion):
+ *   LBF_OBJ_FROZEN_FRACTION  J = sum f_s psi / sum psi, the frozen fraction
+ *                            of the freezing material;
+ *   LBF_OBJ_FRONT            J = sum f_s psi / (cells per wall layer), the
+ *                            front position as a volume-equivalent solid
+ *                            thickness (out[3N+2] of lbf_diagnostics). */
+#define LBF_OBJ_FROZEN_FRACTION 0
+#define LBF_OBJ_FRONT 1
+/* The objective of the context's current state into *J (may be NULL);
+ * resets the gradient and sets the adjoint state to dJ/dx^K.  LBF_EINVAL
+ * for an unknown objective, or for the frozen fraction of a state that
+ * holds no freezing material. */
+lbf_status lbf_adjoint_seed_objective(lbf_adj* adj, int objective, double* J);
+/* lbf_adjoint_seed_objective with LBF_OBJ_FROZEN_FRACTION. */
 lbf_status lbf_adjoint_seed(lbf_adj* adj, double* J);
 /* One reverse step: state = device state x^n (layout of lbf_state_to_device)
  * of the step whose output's adjoint is current; afterwards the adjoint of

@@ -1,15 +1,16 @@
 """Reverse mode of the coupled-LB step (include/lbfreeze.h, lbf_adjoint_*).
 
-Gradient of the frozen fraction of the freezing material at the end of a
-run, J = sum f_s psi / sum psi, with respect to the wall temperatures, the
-latent heats and the wetting cosines, by the hand-written discrete adjoint
-of every step (2D, float32 or float64).  Long runs use checkpoint-and-
+Gradient of an objective of the state at the end of a run -- the frozen
+fraction of the freezing material, J = sum f_s psi / sum psi, or the front
+position, J = sum f_s psi / (cells per wall layer) -- with respect to the
+wall temperatures, the latent heats and the wetting cosines, by the
+hand-written discrete adjoint of every step (2D, float32 or float64).  Long runs use checkpoint-and-
 recompute: the forward run keeps the device state every ``window`` steps;
 the reverse sweep re-runs each window forward from its checkpoint, keeping
 its states on the device, and then steps the adjoint back through it.
 
 :class:`FrozenFraction` exposes this as a ``torch.autograd.Function`` of
-(T_w, latent[N], cos_theta[N, N]); derived parameters such as the Stefan
+(T_w, latent[N], cos_theta[N, N]), for either objective; derived parameters such as the Stefan
 number (L = C (T_melt - T_w) / Ste) or the contact angle (cos_theta) are
 composed in torch around it.
 """
@@ -23,6 +24,7 @@ import numpy as np
 from .lbfreeze import LBF_OK, LbfError, Solver, _PD, _ptr, lib, make_params
 
 NPAR = 22
+OBJECTIVES = {"frozen_fraction": 0, "front": 1}
 
 
 class Adjoint:
@@ -46,9 +48,12 @@ class Adjoint:
     def _check(self, s):
         self.solver._check(s)
 
-    def seed(self) -> float:
+    def seed(self, objective: str = "frozen_fraction") -> float:
+        """Objective of the current state ("frozen_fraction" or "front")."""
+        if objective not in OBJECTIVES:
+            raise ValueError(f"objective must be one of {sorted(OBJECTIVES)}")
         J = np.zeros(1)
-        self._check(lib().lbf_adjoint_seed(self._h, _ptr(J)))
+        self._check(lib().lbf_adjoint_seed_objective(self._h, OBJECTIVES[objective], _ptr(J)))
         return float(J[0])
 
     def step(self, state, next_state=None) -> None:
@@ -107,7 +112,8 @@ def forward_with_checkpoints(solver: Solver, case: dict, nsteps: int, window: in
     return ck
 
 
-def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = None) -> tuple:
+def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = None,
+                  objective: str = "frozen_fraction") -> tuple:
     """With the final state current: J and its gradient (dict) by the
     reverse steps, re-running each window forward from its checkpoint
     straight into a device tape (the solver's own state is not touched).
@@ -124,7 +130,7 @@ def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = N
             ev.append(e)
 
     adj = Adjoint(solver)
-    J = adj.seed()
+    J = adj.seed(objective)
     final = _states(solver, 1)
     solver.lbf_state_to_device(final[0])
     tape = _states(solver, max(1, min(window, nsteps) - 1))
@@ -179,11 +185,13 @@ def case_with(case: dict, T_w=None, latent=None, cos_theta=None) -> dict:
     return c
 
 
-def frozen_fraction_and_gradient(case: dict, nsteps: int, window: int = 50, device: int = 0):
-    """Forward run with checkpoints, then the reverse sweep: (J, gradient)."""
+def frozen_fraction_and_gradient(case: dict, nsteps: int, window: int = 50, device: int = 0,
+                                 objective: str = "frozen_fraction"):
+    """Forward run with checkpoints, then the reverse sweep: (J, gradient)
+    of the objective ("frozen_fraction" or "front")."""
     s = Solver(case["params"], device=device)
     ck = forward_with_checkpoints(s, case, nsteps, window)
-    J, g = reverse_sweep(s, ck, nsteps, window)
+    J, g = reverse_sweep(s, ck, nsteps, window, objective=objective)
     s.close()
     return J, g
 
@@ -192,12 +200,13 @@ def _torch_function():
     import torch
 
     class FrozenFraction(torch.autograd.Function):
-        """J = frozen fraction after nsteps, as a function of T_w (0-d),
-        latent (N,) and cos_theta (N, N) float64 CPU tensors.  The forward
-        keeps checkpoints on the GPU; backward runs the reverse sweep."""
+        """J = the objective after nsteps (frozen fraction or front
+        position), as a function of T_w (0-d), latent (N,) and cos_theta
+        (N, N) float64 CPU tensors.  The forward keeps checkpoints on the
+        GPU; backward runs the reverse sweep."""
 
         @staticmethod
-        def forward(ctx, T_w, latent, cos_theta, case, nsteps, window, device=0):
+        def forward(ctx, T_w, latent, cos_theta, case, nsteps, window, device=0, objective="frozen_fraction"):
             c = case_with(case, float(T_w), latent.detach().cpu().numpy(),
                           cos_theta.detach().cpu().numpy())
             s = Solver(c["params"], device=device)
@@ -207,21 +216,22 @@ def _torch_function():
             frz = [p for p in range(N) if c["params"]["freezes"][p]]
             area = s.shape[2] * (s.shape[1] if s.dim == 3 else 1)
             B = float(sum(d["vol"][p] for p in frz))
-            J = d["front"] * area / B
+            J = d["front"] if objective == "front" else d["front"] * area / B
             ctx.solver, ctx.ck, ctx.nsteps, ctx.window = s, ck, nsteps, window
+            ctx.objective = objective
             ctx.shapes = (latent.shape, cos_theta.shape)
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gJ):
-            _, g = reverse_sweep(ctx.solver, ctx.ck, ctx.nsteps, ctx.window)
+            _, g = reverse_sweep(ctx.solver, ctx.ck, ctx.nsteps, ctx.window, objective=ctx.objective)
             N = ctx.solver.N
             gT = torch.tensor(g["T_face"][0], dtype=torch.float64) * gJ
             gL = torch.tensor(g["latent"][:N], dtype=torch.float64) * gJ
             gC = torch.tensor(g["cos_theta"], dtype=torch.float64) * gJ
             ctx.solver.close()
             ctx.solver = ctx.ck = None
-            return gT, gL, gC, None, None, None, None
+            return gT, gL, gC, None, None, None, None, None
 
     return FrozenFraction
 
@@ -230,8 +240,18 @@ _FF = None
 
 
 def frozen_fraction(T_w, latent, cos_theta, case: dict, nsteps: int, window: int = 50, device: int = 0):
-    """torch entry point: J(T_w, latent, cos_theta) with autograd support."""
+    """torch entry point: the frozen fraction J(T_w, latent, cos_theta) with
+    autograd support."""
     global _FF
     if _FF is None:
         _FF = _torch_function()
-    return _FF.apply(T_w, latent, cos_theta, case, nsteps, window, device)
+    return _FF.apply(T_w, latent, cos_theta, case, nsteps, window, device, "frozen_fraction")
+
+
+def front_position(T_w, latent, cos_theta, case: dict, nsteps: int, window: int = 50, device: int = 0):
+    """torch entry point: the front position s(T_w, latent, cos_theta) =
+    sum f_s psi / (cells per wall layer) with autograd support."""
+    global _FF
+    if _FF is None:
+        _FF = _torch_function()
+    return _FF.apply(T_w, latent, cos_theta, case, nsteps, window, device, "front")

@@ -222,7 +222,6 @@ __host__ __device__ inline void nb_fields(const AdjArgs<C>& a, const KParams& P,
                                           typename C::R& rho, typename C::R* up) {
   using R = typename C::R;
   using Lt = typename C::L;
-  using L = AdjLayout<C>;
   constexpr int NP = C::NP;
   const long long nc = P.ncell;
   int lat = wrap1(gx + Lt::cl0(i), P.nx);
@@ -997,12 +996,16 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
   adj_gather_cell<C>(a, P, cell, seed, gpar, g);
 }
 
-// Objective J = sum f_s psi / sum psi (frozen fraction of the freezing
-// material) at the final state: adjoints of phi_p, f_s into the own planes
-// (A = sum f_s psi, B = sum psi, from the moments).
+// Objectives of the final state, both of the form J = A / D with
+// A = sum f_s psi over cells (psi the freezing phases' fraction):
+//   frozen fraction  D = sum psi:                shift = A / D, scale = 1 / D
+//   front position   D = cells per wall layer:   shift = 0,     scale = 1 / D
+// (the volume-equivalent solid thickness).  Adjoints of phi_p (freezing
+// phases) and f_s into the own planes: dJ/dphi_p = (f_s - shift) scale,
+// dJ/df_s = psi scale.
 template <class C>
-__host__ __device__ inline void adj_seed_cell(const AdjArgs<C>& a, const KParams& P, int cell, double A,
-                                              double B) {
+__host__ __device__ inline void adj_seed_cell(const AdjArgs<C>& a, const KParams& P, int cell, double shift,
+                                              double scale) {
   using R = typename C::R;
   using L = AdjLayout<C>;
   constexpr int NP = C::NP;
@@ -1012,8 +1015,8 @@ __host__ __device__ inline void adj_seed_cell(const AdjArgs<C>& a, const KParams
     if (P.freezes[p]) psi += wplane(a, L::M_PHI + p, nc)[cell];
   const R fs = wplane(a, L::M_FS, nc)[cell];
   for (int p = 0; p < NP; ++p)
-    wplane(a, L::O_PHI + p, nc)[cell] = P.freezes[p] ? R((double(fs) - A / B) / B) : R(0);
-  wplane(a, L::O_FS, nc)[cell] = R(double(psi) / B);
+    wplane(a, L::O_PHI + p, nc)[cell] = P.freezes[p] ? R((double(fs) - shift) * scale) : R(0);
+  wplane(a, L::O_FS, nc)[cell] = R(double(psi) * scale);
 }
 
 // Dependence of the initial state on the latent heats: the rest enthalpy

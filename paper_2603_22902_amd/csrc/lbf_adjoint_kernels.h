@@ -5,7 +5,7 @@
 //   adj_gather_kernel        pass 3: transpose of the finite differences and
 //                            of the moments (SEED: start from the objective)
 //   adj_objective_kernel     sums A = sum f_s psi, B = sum psi of a state
-//   adj_seed_kernel          adjoints of phi, f_s of J = A / B
+//   adj_seed_kernel          adjoints of phi, f_s of the objective
 //   adj_init_latent_kernel   dependence of the initial state on L_p
 //
 // (The block partials are summed into the gradient by a kernel of the API
@@ -192,10 +192,10 @@ __global__ void __launch_bounds__(ADJ_THREADS)
 
 template <class C>
 __global__ void __launch_bounds__(ADJ_THREADS)
-    adj_seed_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double A, double B) {
+    adj_seed_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double shift, double scale) {
   const KParams& P = *kp;
   const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
-  if (cell < P.ncell) adj_seed_cell<C>(a, P, cell, A, B);
+  if (cell < P.ncell) adj_seed_cell<C>(a, P, cell, shift, scale);
 }
 
 template <class C>
@@ -211,7 +211,8 @@ __global__ void __launch_bounds__(ADJ_THREADS)
 }
 
 // Launchers.  pass: 0 moments, 1 collide, 2 gather, 3 seed gather,
-// 4 objective partials, 5 seed (A, B), 6 initial-state latent term.
+// 4 objective partials, 5 seed (A = shift, B = scale), 6 initial-state
+// latent term.
 template <int DIM, int NP, typename S, typename R>
 inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* lpin, const S* lain, S* lpout,
                                  S* laout, const S* mom, void* work, const KParams& P, const KParams* dP,

@@ -558,9 +558,13 @@ lbf_status adj_reduce(lbf_adj* a, const double* part, int nv, int nrows, double*
     if (s_ != LBF_OK) return s_;          \
   } while (0)
 
-lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) {
+lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) { return lbf_adjoint_seed_objective(a, LBF_OBJ_FROZEN_FRACTION, J); }
+
+lbf_status lbf_adjoint_seed_objective(lbf_adj* a, int objective, double* J) {
   if (!a) return LBF_EINVAL;
   lbf_ctx* c = a->c;
+  if (objective != LBF_OBJ_FROZEN_FRACTION && objective != LBF_OBJ_FRONT)
+    return fail(c, LBF_EINVAL, "unknown objective");
   if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
   const void* pin = pop_ptr(c, c->cur);
   const void* ain = aux_ptr(c, c->cur);
@@ -570,15 +574,20 @@ lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) {
   double AB[2];
   HIPCHK(c, hipMemcpyAsync(AB, adj_obj(a), sizeof AB, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-  if (!(AB[1] > 0.0)) return fail(c, LBF_EINVAL, "no freezing material in the state (sum psi = 0)");
+  if (objective == LBF_OBJ_FROZEN_FRACTION && !(AB[1] > 0.0))
+    return fail(c, LBF_EINVAL, "no freezing material in the state (sum psi = 0)");
+  // J = A / D: frozen fraction D = sum psi, front position D = cells per
+  // wall layer
+  const double D = objective == LBF_OBJ_FRONT ? double(c->kp.area) : AB[1];
+  const double shift = objective == LBF_OBJ_FRONT ? 0.0 : AB[0] / D;
   const int nz = a->lay.nblocks * lbf::NPAR;
   hipLaunchKernelGGL(adj_zero_kernel, dim3((nz + 255) / 256), dim3(256), 0, c->stream, adj_part(a), nz);
   HIPCHK(c, hipGetLastError(), "adjoint zero");
-  ADJCHK(adj_pass(a, 5, pin, ain, nullptr, nullptr, nullptr, nullptr, AB[0], AB[1]));
+  ADJCHK(adj_pass(a, 5, pin, ain, nullptr, nullptr, nullptr, nullptr, shift, 1.0 / D));
   ADJCHK(adj_pass(a, 3, pin, ain, nullptr, nullptr, adj_lp(a, 0), adj_la(a, 0), 0.0, 0.0));
   a->cur = 0;
   a->seeded = true;
-  a->J = AB[0] / AB[1];
+  a->J = AB[0] / D;
   if (J) *J = a->J;
   return LBF_OK;
 }

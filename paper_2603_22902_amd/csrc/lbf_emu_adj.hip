@@ -58,9 +58,9 @@ void forward_step(std::vector<typename C::S>& popA, std::vector<typename C::S>& 
   }
 }
 
-// Frozen fraction J = sum f_s psi / sum psi of a state, from the moments.
+// A = sum f_s psi and B = sum psi of a state, from the moments.
 template <class C>
-void objective(const AdjArgs<C>& a, const KParams& P, double& A, double& B) {
+void objective_sums(const AdjArgs<C>& a, const KParams& P, double& A, double& B) {
   using L = AdjLayout<C>;
   const long long nc = P.ncell;
   A = B = 0.0;
@@ -111,7 +111,8 @@ void gather_tiled(const AdjArgs<C>& a, const KParams& P, double* gpar) {
 }
 
 template <int DIM, int NP, typename S, typename R>
-int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, double* J, double* grad) {
+int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, int objective, double* J,
+        double* grad) {
   using C = CfgOf<DIM, NP, S, R>;
   const KParams P = make_kparams(prm);
   const long long nc = P.ncell;
@@ -141,9 +142,11 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, d
   a.laout = laA.data();
   for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
   double A, B;
-  objective<C>(a, P, A, B);
-  *J = A / B;
-  for (int c = 0; c < (int)nc; ++c) adj_seed_cell<C>(a, P, c, A, B);
+  objective_sums<C>(a, P, A, B);
+  const double D = objective == LBF_OBJ_FRONT ? double(P.area) : B;
+  const double shift = objective == LBF_OBJ_FRONT ? 0.0 : A / D;
+  *J = A / D;
+  for (int c = 0; c < (int)nc; ++c) adj_seed_cell<C>(a, P, c, shift, 1.0 / D);
   for (int c = 0; c < (int)nc; ++c) adj_gather_cell<C>(a, P, c, true, gpar.data());
   for (int s = nsteps - 1; s >= 0; --s) {
     a.pin = pops[s].data();
@@ -180,29 +183,32 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, d
 }
 
 template <int DIM, typename S, typename R>
-int run_n(const lbf_params* prm, const double* phi, const double* T, int nsteps, double* J, double* grad) {
+int run_n(const lbf_params* prm, const double* phi, const double* T, int nsteps, int objective, double* J,
+          double* grad) {
   switch (prm->nphase) {
-    case 1: return run<DIM, 1, S, R>(prm, phi, T, nsteps, J, grad);
-    case 2: return run<DIM, 2, S, R>(prm, phi, T, nsteps, J, grad);
-    case 3: return run<DIM, 3, S, R>(prm, phi, T, nsteps, J, grad);
-    case 4: return run<DIM, 4, S, R>(prm, phi, T, nsteps, J, grad);
+    case 1: return run<DIM, 1, S, R>(prm, phi, T, nsteps, objective, J, grad);
+    case 2: return run<DIM, 2, S, R>(prm, phi, T, nsteps, objective, J, grad);
+    case 3: return run<DIM, 3, S, R>(prm, phi, T, nsteps, objective, J, grad);
+    case 4: return run<DIM, 4, S, R>(prm, phi, T, nsteps, objective, J, grad);
   }
   return -1;
 }
 
 }  // namespace
 
-// Frozen fraction J after nsteps from an equilibrium start (phi, T; u = 0,
-// p = 0) and its gradient: grad[0..1] d J / d T_face, grad[2..5] d J / d L_p,
-// grad[6..21] d J / d cth[p][q] (row-major, MAXP x MAXP).
+// Objective J (LBF_OBJ_FROZEN_FRACTION or LBF_OBJ_FRONT) after nsteps from
+// an equilibrium start (phi, T; u = 0, p = 0) and its gradient:
+// grad[0..1] d J / d T_face, grad[2..5] d J / d L_p, grad[6..21]
+// d J / d cth[p][q] (row-major, MAXP x MAXP).
 extern "C" int lbf_emu_adjoint(const lbf_params* prm, const double* phi, const double* T, int nsteps,
-                               double* J, double* grad) {
+                               int objective, double* J, double* grad) {
   if (!check_params(prm).empty() || nsteps < 0) return -1;
+  if (objective != LBF_OBJ_FROZEN_FRACTION && objective != LBF_OBJ_FRONT) return -3;
   lbf_params q = *prm;
   if (q.dim == 2) q.nz = 1;
-  if (q.dim == 2 && q.precision == LBF_FP64) return run_n<2, double, double>(&q, phi, T, nsteps, J, grad);
-  if (q.dim == 2 && q.precision == LBF_FP32) return run_n<2, float, float>(&q, phi, T, nsteps, J, grad);
-  if (q.dim == 3 && q.precision == LBF_FP64) return run_n<3, double, double>(&q, phi, T, nsteps, J, grad);
-  if (q.dim == 3 && q.precision == LBF_FP32) return run_n<3, float, float>(&q, phi, T, nsteps, J, grad);
+  if (q.dim == 2 && q.precision == LBF_FP64) return run_n<2, double, double>(&q, phi, T, nsteps, objective, J, grad);
+  if (q.dim == 2 && q.precision == LBF_FP32) return run_n<2, float, float>(&q, phi, T, nsteps, objective, J, grad);
+  if (q.dim == 3 && q.precision == LBF_FP64) return run_n<3, double, double>(&q, phi, T, nsteps, objective, J, grad);
+  if (q.dim == 3 && q.precision == LBF_FP32) return run_n<3, float, float>(&q, phi, T, nsteps, objective, J, grad);
   return -2;
 }

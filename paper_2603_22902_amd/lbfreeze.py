@@ -71,6 +71,7 @@ def lib():
         L.lbf_adjoint_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_adjoint_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.lbf_adjoint_seed.argtypes = [vp, _PD]
+        L.lbf_adjoint_seed_objective.argtypes = [vp, ctypes.c_int, _PD]
         L.lbf_adjoint_step.argtypes = [vp, vp, vp]
         L.lbf_adjoint_finish.argtypes = [vp, vp]
         L.lbf_adjoint_gradient.argtypes = [vp, _PD]
@@ -103,7 +104,7 @@ def lib():
                      "lbf_diagnostics", "lbf_snapshot_bytes", "lbf_save_state", "lbf_load_state",
                      "lbf_step_count", "lbf_destroy", "lbf_state_device_bytes",
                      "lbf_state_to_device", "lbf_state_from_device", "lbf_step_states", "lbf_adjoint_bytes",
-                     "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_step", "lbf_adjoint_finish",
+                     "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_seed_objective", "lbf_adjoint_step", "lbf_adjoint_finish",
                      "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy",
                      "lbf_batch_bytes", "lbf_batch_create", "lbf_batch_set_tiles", "lbf_batch_tune",
                      "lbf_batch_step", "lbf_batch_capture", "lbf_batch_replay", "lbf_batch_destroy"):

@@ -1,7 +1,9 @@
 """Cases and finite-difference helpers of the reverse-step tests.
 
 J is the frozen fraction of the freezing material after n steps from an
-equilibrium start, sum f_s psi / sum psi; the parameters are T_face[0]
+equilibrium start, sum f_s psi / sum psi, or the front position, the
+volume-equivalent solid thickness sum f_s psi / (cells per wall layer);
+the parameters are T_face[0]
 (the cold wall), the latent heats of the freezing phases and the wetting
 cosines (perturbed antisymmetrically, as the wetting rule requires)."""
 import copy
@@ -59,6 +61,15 @@ def oracle_J(case, params, nsteps):
     N = params["nphase"]
     psi = sum(m["phi"][p] for p in range(N) if params["freezes"][p])
     return float(((1.0 - m["fl"]) * psi).sum() / psi.sum())
+
+
+def oracle_front(case, params, nsteps):
+    """Front position of the FP64 oracle run with the given parameters,
+    from the oracle's own conservation diagnostics."""
+    o = oracle.Oracle(params)
+    o.init_case({"phi": case["phi"], "T": case["T"]})
+    o.step(nsteps)
+    return float(o.diagnostics()["front"])
 
 
 def central(fn, params, key, idx, h):

@@ -29,7 +29,7 @@ def _lib():
                                      ctypes.c_int, _PD, _PD, _PD]
         _emu.lbf_emu_adjoint.restype = ctypes.c_int
         _emu.lbf_emu_adjoint.argtypes = [ctypes.POINTER(lbfreeze.lbf_params), _PD, _PD, ctypes.c_int,
-                                         _PD, _PD]
+                                         ctypes.c_int, _PD, _PD]
     return _emu
 
 
@@ -59,16 +59,21 @@ def run(case, nsteps):
     return pop, aux, m
 
 
-def adjoint(params, phi, T, nsteps):
+OBJECTIVES = {"frozen_fraction": 0, "front": 1}
+
+
+def adjoint(params, phi, T, nsteps, objective="frozen_fraction"):
     """Emulated forward run from an equilibrium start (u = p = 0) and the
-    reverse sweep: (J, grad[22]) with J the frozen fraction of the final
-    state and grad as lbf_adjoint_gradient."""
+    reverse sweep: (J, grad[22]) with J the objective of the final state
+    (the frozen fraction, or the front position sum f_s psi per wall-layer
+    cell) and grad as lbf_adjoint_gradient."""
     P = lbfreeze.make_params(params)
     J = np.zeros(1)
     g = np.zeros(22)
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     T = np.ascontiguousarray(T, dtype=np.float64)
-    rc = _lib().lbf_emu_adjoint(ctypes.byref(P), _p(phi), _p(T), int(nsteps), _p(J), _p(g))
+    rc = _lib().lbf_emu_adjoint(ctypes.byref(P), _p(phi), _p(T), int(nsteps),
+                                 OBJECTIVES[objective], _p(J), _p(g))
     if rc != 0:
         raise RuntimeError(f"lbf_emu_adjoint failed ({rc})")
     return float(J[0]), g

@@ -1,7 +1,7 @@
 """GPU reverse step (lbf_adjoint_* through the C ABI): gradients of the
-frozen fraction against the host emulator of the same passes, against
-central differences of the FP64 oracle, across checkpoint windows, in
-float32, and through torch autograd."""
+frozen fraction and of the front position against the host emulator of the
+same passes, against central differences of the FP64 oracle, across
+checkpoint windows, in float32, and through torch autograd."""
 import math
 
 import numpy as np
@@ -9,14 +9,14 @@ import pytest
 
 import emulator
 import synth
-from adjoint_util import CASES, central, checks, make_case, oracle_J
+from adjoint_util import CASES, central, checks, make_case, oracle_front, oracle_J
 
 pytestmark = pytest.mark.gpu
 
 
-def _grad(case, nsteps, window):
+def _grad(case, nsteps, window, objective="frozen_fraction"):
     from paper_2603_22902_amd.adjoint import frozen_fraction_and_gradient
-    return frozen_fraction_and_gradient(case, nsteps, window)
+    return frozen_fraction_and_gradient(case, nsteps, window, objective=objective)
 
 
 @pytest.mark.parametrize("spec", CASES, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
@@ -36,6 +36,26 @@ def test_gpu_adjoint_matches_oracle_gradient():
     n = 20
     J, g = _grad(case, n, 7)
     fj = lambda q: oracle_J(case, q, n)
+    for key, idx, h, pick in checks(prm):
+        fd = central(fj, prm, key, idx, h)
+        assert abs(pick(g["raw"]) - fd) <= 1e-4 * abs(fd) + 1e-10, (key, idx, pick(g["raw"]), fd)
+
+
+def test_gpu_front_gradient_matches_emulator_and_oracle():
+    """The front-position objective (sum f_s psi per wall-layer cell): the
+    float64 sweep against the emulator, and against central differences of
+    the FP64 oracle's diagnostic front."""
+    case = make_case(*CASES[1])
+    prm = case["params"]
+    n = 20
+    print("front objective", CASES[1], flush=True)
+    J, g = _grad(case, n, 7, objective="front")
+    Je, ge = emulator.adjoint(prm, case["phi"], case["T"], n, objective="front")
+    assert abs(J - Je) <= 1e-13 * max(1.0, Je)
+    assert abs(J - oracle_front(case, prm, n)) <= 1e-12 * max(1.0, J)
+    scale = np.abs(ge).max()
+    assert np.abs(g["raw"] - ge).max() <= 1e-10 * scale, (g["raw"], ge)
+    fj = lambda q: oracle_front(case, q, n)
     for key, idx, h, pick in checks(prm):
         fd = central(fj, prm, key, idx, h)
         assert abs(pick(g["raw"]) - fd) <= 1e-4 * abs(fd) + 1e-10, (key, idx, pick(g["raw"]), fd)
@@ -66,14 +86,15 @@ def test_float32_adjoint_close_to_float64():
     assert err <= 1e-3
 
 
-def test_autograd_stefan_number_and_contact_angle():
+@pytest.mark.parametrize("objective", ["frozen_fraction", "front"])
+def test_autograd_stefan_number_and_contact_angle(objective):
     """torch autograd through the reverse step: J(T_w, Ste, theta) with
     L = C_s (T_melt - T_w) / Ste for the freezing phase and
     cos_theta = [[0, cos t], [-cos t, 0]]; the gradient against central
     differences of GPU forward runs, within 1e-4."""
     import torch
 
-    from paper_2603_22902_amd.adjoint import frozen_fraction
+    from paper_2603_22902_amd.adjoint import frozen_fraction, front_position
 
     base = make_case(*CASES[0])
     prm = base["params"]
@@ -84,7 +105,8 @@ def test_autograd_stefan_number_and_contact_angle():
         L = torch.stack([Cs * (synth.T_MELT - Tw) / Ste, torch.zeros((), dtype=torch.float64)])
         c, s0 = torch.cos(th), torch.zeros((), dtype=torch.float64)
         ct = torch.stack([torch.stack([s0, c]), torch.stack([-c, s0])])
-        return frozen_fraction(Tw, L, ct, base, n, 10)
+        fn = front_position if objective == "front" else frozen_fraction
+        return fn(Tw, L, ct, base, n, 10)
 
     x = [torch.tensor(v, dtype=torch.float64, requires_grad=True)
          for v in (prm["T_face"][0], 0.1, math.radians(70.0))]
