@@ -274,6 +274,46 @@ lbf_status lbf_batch_replay(lbf_batch* b, int times);
 /* Release the batch (not the contexts or the buffer).  NULL is a no-op. */
 lbf_status lbf_batch_destroy(lbf_batch* b);
 
+/* Packed batch states (checkpoints and the tape of a batched reverse
+ * sweep): every case's device state (layout of lbf_state_to_device) in the
+ * order of the contexts given to lbf_batch_create, each at a 256-byte
+ * aligned offset; lbf_batch_state_bytes is the size of one.  The caller owns
+ * the device memory (256-byte aligned).  lbf_batch_state_to_device copies
+ * the members' current states; lbf_batch_step_states advances every case
+ * by one step from src to dst (distinct) in one launch per pass and phase
+ * count, with the bitwise result of lbf_step_states per case; neither
+ * touches the members' own states.  Asynchronous on the batch's stream. */
+lbf_status lbf_batch_state_bytes(const lbf_batch* b, size_t* bytes);
+lbf_status lbf_batch_state_to_device(lbf_batch* b, void* dst);
+lbf_status lbf_batch_step_states(lbf_batch* b, const void* src, void* dst);
+
+/* Batched reverse step (2D, float32 or float64; the objectives and the
+ * gradient of the single-case reverse step, per case).  The two per-step
+ * passes run as one launch each per phase count over all cases; each case
+ * keeps its single-case block decomposition and gradient rows, so its J and
+ * gradient are bitwise those of a single-case sweep over the same states.
+ * Sweep: lbf_batch_adjoint_seed with the packed final state x^K; for
+ * n = K-1 .. 0, lbf_batch_adjoint_step with the packed x^n and x^{n+1}
+ * (both required); lbf_batch_adjoint_finish with the packed x^0;
+ * lbf_batch_adjoint_gradient.  The caller allocates lbf_batch_adjoint_bytes
+ * of device memory (256-byte aligned: case tables and each case's adjoint
+ * buffer) for the object's lifetime, which must not exceed the batch's.
+ * All calls run on the batch's stream; seed and gradient synchronise it.
+ * LBF_ENOTSUP if a member has no reverse step (3D, or float32 storage with
+ * float64 arithmetic). */
+typedef struct lbf_batch_adj lbf_batch_adj;
+lbf_status lbf_batch_adjoint_bytes(const lbf_batch* b, size_t* bytes);
+lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, lbf_batch_adj** out);
+/* objective: LBF_OBJ_FROZEN_FRACTION or LBF_OBJ_FRONT; J (may be NULL)
+ * receives one value per case, in caller order. */
+lbf_status lbf_batch_adjoint_seed(lbf_batch_adj* adj, int objective, const void* state, double* J);
+lbf_status lbf_batch_adjoint_step(lbf_batch_adj* adj, const void* state, const void* next);
+lbf_status lbf_batch_adjoint_finish(lbf_batch_adj* adj, const void* state0);
+/* grad[ncase][22], caller order, each row as lbf_adjoint_gradient. */
+lbf_status lbf_batch_adjoint_gradient(lbf_batch_adj* adj, double* grad);
+/* Release the object (not the buffer).  NULL is a no-op. */
+lbf_status lbf_batch_adjoint_destroy(lbf_batch_adj* adj);
+
 /* Steps taken since lbf_init_fields (restored by lbf_load_state). */
 lbf_status lbf_step_count(const lbf_ctx* ctx, long long* steps);
 

@@ -2,12 +2,21 @@
 solvers advance together, one moments and one collide launch per phase count
 and time step, optionally replayed from a captured HIP graph; the row tile of
 each phase count is picked by the library's autotuner.  Each case's result
-is bitwise that of stepping its :class:`Solver` alone."""
+is bitwise that of stepping its :class:`Solver` alone.
+
+The batched reverse sweep (:func:`batch_forward_with_checkpoints`,
+:func:`batch_reverse_sweep`) differentiates every case's objective at once:
+packed batch states hold the checkpoints and the tape, each recomputed step
+and each reverse step is one launch per pass and phase count over all
+cases, and every case's gradient is bitwise that of its single-case sweep."""
 from __future__ import annotations
 
 import ctypes
 
-from .lbfreeze import LBF_OK, LbfError, Solver, lib
+import numpy as np
+
+from .adjoint import NPAR, OBJECTIVES
+from .lbfreeze import LBF_OK, LbfError, Solver, _ptr, lib
 
 
 class Batch:
@@ -64,6 +73,30 @@ class Batch:
     def synchronize(self) -> None:
         self.stream.synchronize()
 
+    # ----- packed batch states (checkpoints and tapes of a batched sweep)
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t(0)
+        self._check(lib().lbf_batch_state_bytes(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def states(self, k: int):
+        """k packed batch states, one per row of a uint8 device tensor."""
+        import torch
+
+        t = torch.empty((k, self.state_bytes()), dtype=torch.uint8, device=self.solvers[0].device)
+        if t.data_ptr() & 255:
+            raise RuntimeError("packed batch states need a 256-byte aligned allocation")
+        return t
+
+    def state_to_device(self, dst) -> None:
+        """Copy every member's current state into the packed state dst."""
+        self._check(lib().lbf_batch_state_to_device(self._h, ctypes.c_void_p(dst.data_ptr())))
+
+    def step_states(self, src, dst) -> None:
+        """One batched step from packed state src to dst (members untouched)."""
+        self._check(lib().lbf_batch_step_states(self._h, ctypes.c_void_p(src.data_ptr()),
+                                                ctypes.c_void_p(dst.data_ptr())))
+
     def close(self):
         if getattr(self, "_h", None):
             lib().lbf_batch_destroy(self._h)
@@ -74,3 +107,121 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class BatchAdjoint:
+    """Batched reverse step over a :class:`Batch` (its stream and cases)."""
+
+    def __init__(self, batch: Batch):
+        import torch
+
+        self.batch = batch
+        n = ctypes.c_size_t(0)
+        st = lib().lbf_batch_adjoint_bytes(batch._h, ctypes.byref(n))
+        if st != LBF_OK:
+            raise LbfError(st, "lbf_batch_adjoint_bytes: the batched reverse step needs 2D float32 or float64 cases")
+        nbytes = int(n.value)
+        self.buffer = torch.empty(nbytes + 256, dtype=torch.uint8, device=batch.solvers[0].device)
+        aligned = (self.buffer.data_ptr() + 255) & ~255
+        h = ctypes.c_void_p(0)
+        batch._check(lib().lbf_batch_adjoint_create(batch._h, ctypes.c_void_p(aligned), nbytes, ctypes.byref(h)))
+        self._h = h
+
+    def seed(self, state, objective: str = "frozen_fraction") -> np.ndarray:
+        """Objective of every case of the packed state (caller order)."""
+        if objective not in OBJECTIVES:
+            raise ValueError(f"objective must be one of {sorted(OBJECTIVES)}")
+        J = np.zeros(len(self.batch.solvers))
+        self.batch._check(lib().lbf_batch_adjoint_seed(self._h, OBJECTIVES[objective],
+                                                        ctypes.c_void_p(state.data_ptr()), _ptr(J)))
+        return J
+
+    def step(self, state, next_state) -> None:
+        self.batch._check(lib().lbf_batch_adjoint_step(self._h, ctypes.c_void_p(state.data_ptr()),
+                                                        ctypes.c_void_p(next_state.data_ptr())))
+
+    def finish(self, state0) -> None:
+        self.batch._check(lib().lbf_batch_adjoint_finish(self._h, ctypes.c_void_p(state0.data_ptr())))
+
+    def gradient(self) -> np.ndarray:
+        """(ncase, 22) rows as lbf_adjoint_gradient."""
+        g = np.zeros((len(self.batch.solvers), NPAR))
+        self.batch._check(lib().lbf_batch_adjoint_gradient(self._h, _ptr(g)))
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbf_batch_adjoint_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_forward_with_checkpoints(batch: Batch, nsteps: int, window: int, graph: bool = False):
+    """nsteps batched steps from the members' current states; returns the
+    packed states at steps 0, window, 2 window, ... (one row each).  graph:
+    even stretches replay the captured two-step graph (capture first)."""
+    nck = (nsteps + window - 1) // window if nsteps > 0 else 1
+    ck = batch.states(nck)
+    done = 0
+    for k in range(nck):
+        batch.state_to_device(ck[k])
+        n = min(window, nsteps - done)
+        if n > 0:
+            if graph:
+                batch.replay(n // 2)
+                batch.step(n % 2)
+            else:
+                batch.step(n)
+            done += n
+    return ck
+
+
+def batch_reverse_sweep(batch: Batch, ck, nsteps: int, window: int, objective: str = "frozen_fraction",
+                        timing: dict = None) -> tuple:
+    """With the members at the final state: (J[ncase], grad[ncase, 22]) by
+    batched reverse steps, re-running each window from its checkpoint into a
+    packed tape with batched steps.  timing (a dict) receives the
+    milliseconds of recomputation and of reverse steps (events on the
+    batch's stream)."""
+    import torch
+
+    ev = []
+
+    def mark():
+        if timing is not None:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(batch.stream)
+            ev.append(e)
+
+    adj = BatchAdjoint(batch)
+    final = batch.states(1)
+    batch.state_to_device(final[0])
+    J = adj.seed(final[0], objective)
+    tape = batch.states(max(1, min(window, nsteps) - 1))
+    for k in range(ck.shape[0] - 1, -1, -1):
+        start = k * window
+        n = min(window, nsteps - start)
+        if n <= 0:
+            continue
+        nxt = ck[k + 1] if start + n < nsteps else final[0]
+        states = [ck[k]] + [tape[j] for j in range(n - 1)] + [nxt]
+        mark()
+        for j in range(1, n):
+            batch.step_states(states[j - 1], states[j])
+        mark()
+        for j in range(n - 1, -1, -1):
+            adj.step(states[j], states[j + 1])
+        mark()
+    adj.finish(ck[0])
+    g = adj.gradient()
+    adj.close()
+    if timing is not None:
+        batch.synchronize()
+        timing["recompute_ms"] = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(0, len(ev), 3))
+        timing["reverse_ms"] = sum(ev[i + 1].elapsed_time(ev[i + 2]) for i in range(0, len(ev), 3))
+    return J, g

@@ -26,12 +26,12 @@ namespace lbf {
 
 constexpr int ADJ_THREADS = 256;
 
-// Sum NV per-thread values over the block into part[blockIdx.x][NV]
+// Sum NV per-thread values over a block of NT threads into row[0..NV)
 // (ACC: add to the row, which accumulates this block's terms over the
-// reverse steps; else overwrite).
-template <int NV, bool ACC>
-__device__ inline void block_sum(const double* g, double* part) {
-  __shared__ double red[ADJ_THREADS / 64][NV];
+// reverse steps; else overwrite).  Fixed order: wave shuffles, then waves.
+template <int NV, bool ACC, int NT = ADJ_THREADS>
+__device__ inline void block_sum_to(const double* g, double* row) {
+  __shared__ double red[NT / 64][NV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -44,10 +44,16 @@ __device__ inline void block_sum(const double* g, double* part) {
   if ((int)threadIdx.x < NV) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < ADJ_THREADS / 64; ++w) s += red[w][threadIdx.x];
-    double* dst = part + (long long)blockIdx.x * NV + threadIdx.x;
+    for (int w = 0; w < NT / 64; ++w) s += red[w][threadIdx.x];
+    double* dst = row + threadIdx.x;
     *dst = ACC ? *dst + s : s;
   }
+}
+
+// The same into part[blockIdx.x][NV].
+template <int NV, bool ACC>
+__device__ inline void block_sum(const double* g, double* part) {
+  block_sum_to<NV, ACC>(g, part + (long long)blockIdx.x * NV);
 }
 
 template <class C>
@@ -115,18 +121,11 @@ __host__ __device__ inline void fda_fill(const AdjArgs<C>& a, const KParams& P, 
   for (int k = 0; k < FdaRing<C>::NF; ++k) r.v[slot(w)][k][f] = wplane(a, L::F_GPHI + k, nc)[cell];
 }
 
+// One block of the tiled gather: the tile and layer chunk bp, its
+// parameter terms added to row (NPAR values).
 template <class C>
-__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
-    adj_gather_tile_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part, int ntx,
-                           int nty, int chunk, int nblocks) {
-  const KParams& P = *kp;
-  __shared__ FdaRing<C> ring;
-  StepArgs<typename C::S> sa;
-  sa.ntx = ntx;
-  sa.nty = nty;
-  sa.chunk = chunk;
-  sa.nblocks = nblocks;
-  const BlockPos bp = block_pos<C>(sa, P, blockIdx.x);
+__device__ inline void gather_tile_block(const AdjArgs<C>& a, const KParams& P, const BlockPos& bp,
+                                         FdaRing<C>& ring, double* row) {
   const int tid = threadIdx.x;
   const int tx = tid % C::TX, ty = tid / C::TX;
   const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
@@ -153,22 +152,25 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
     }
     __syncthreads();
   }
-  // per-block parameter terms (fixed order, as block_sum)
-  __shared__ double red[C::NT / 64][NPAR];
-  const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-  for (int k = 0; k < NPAR; ++k) {
-    double v = g[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[wv][k] = v;
-  }
-  __syncthreads();
-  if (tid < NPAR) {
-    double t = 0.0;
-    for (int w = 0; w < C::NT / 64; ++w) t += red[w][tid];
-    part[(long long)blockIdx.x * NPAR + tid] += t;
-  }
+  block_sum_to<NPAR, true, C::NT>(g, row);
+}
+
+// The row of a block is its tile index (the block number after the XCD
+// remap), so that a batched launch, whose remap spans many cases, fills
+// the same rows in the same order.
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
+    adj_gather_tile_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part, int ntx,
+                           int nty, int chunk, int nblocks) {
+  const KParams& P = *kp;
+  __shared__ FdaRing<C> ring;
+  StepArgs<typename C::S> sa;
+  sa.ntx = ntx;
+  sa.nty = nty;
+  sa.chunk = chunk;
+  sa.nblocks = nblocks;
+  const int t = xcd_remap(blockIdx.x, nblocks);
+  gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, part + (long long)t * NPAR);
 }
 
 template <class C>

@@ -11,6 +11,7 @@
 #include "../../include/lbfreeze.h"
 #include "lbf_adjoint.h"
 #include "lbf_batch.h"
+#include "lbf_batch_adjoint.h"
 #include "lbf_host.h"
 #include "lbf_ops.h"
 
@@ -35,14 +36,18 @@ struct lbf_ctx {
 // device buffer.
 struct lbf_batch_group {
   std::vector<lbf_ctx*> ctx;
-  std::vector<int> cur0;  // buffer of each case at even batch steps
-  int variant;            // row tile BATCH_TILES[variant]
-  int cblocks, mblocks;   // grid sizes of the two passes
-  size_t off;             // case table offset in the device buffer
+  std::vector<int> cur0;        // buffer of each case at even batch steps
+  std::vector<int> user;        // index of each case in the caller's list
+  std::vector<long long> soff;  // offset of each case in a packed batch state
+  int variant;                  // row tile BATCH_TILES[variant]
+  int cblocks, mblocks;         // grid sizes of the two passes
+  size_t off;                   // case table offset in the device buffer
 };
 
 struct lbf_batch {
   lbf_ctx* first;
+  int ncase;
+  size_t state_bytes;  // packed batch state: the cases' device states in caller order
   lbf_batch_group g[lbf::MAXP];
   char* base;
   hipStream_t stream;
@@ -56,7 +61,8 @@ struct lbf_adj {
   lbf_ctx* c;
   lbf::AdjBufLayout lay;
   char* base;
-  int cur;  // adjoint buffer holding the adjoint of the current time level
+  hipStream_t stream;  // the context's stream, or the batch's for a batched sweep
+  int cur;             // adjoint buffer holding the adjoint of the current time level
   bool seeded;
   double J;
 };
@@ -517,6 +523,7 @@ lbf_status lbf_adjoint_create(lbf_ctx* c, void* dev_buf, size_t bytes, lbf_adj**
   a->c = c;
   a->lay = lay;
   a->base = static_cast<char*>(dev_buf);
+  a->stream = c->stream;
   a->cur = 0;
   a->seeded = false;
   a->J = 0.0;
@@ -539,14 +546,14 @@ lbf_status adj_pass(lbf_adj* a, int pass, const void* pin, const void* ain, cons
                     void* lpout, void* laout, double A, double B, const void* mom = nullptr) {
   lbf_ctx* c = a->c;
   HIPCHK(c, c->ops->adjoint(pass, pin, ain, lpin, lain, lpout, laout, mom, adj_work(a), c->kp, kp_ptr(c),
-                            pass == 4 ? adj_opart(a) : adj_part(a), A, B, c->stream),
+                            pass == 4 ? adj_opart(a) : adj_part(a), A, B, a->stream),
          "adjoint kernel");
   return LBF_OK;
 }
 
 lbf_status adj_reduce(lbf_adj* a, const double* part, int nv, int nrows, double* out) {
   lbf_ctx* c = a->c;
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nv), dim3(256), 0, c->stream, part, nrows, nv, out);
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(nv), dim3(256), 0, a->stream, part, nrows, nv, out);
   HIPCHK(c, hipGetLastError(), "adjoint reduction");
   return LBF_OK;
 }
@@ -558,22 +565,19 @@ lbf_status adj_reduce(lbf_adj* a, const double* part, int nv, int nrows, double*
     if (s_ != LBF_OK) return s_;          \
   } while (0)
 
-lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) { return lbf_adjoint_seed_objective(a, LBF_OBJ_FROZEN_FRACTION, J); }
-
-lbf_status lbf_adjoint_seed_objective(lbf_adj* a, int objective, double* J) {
-  if (!a) return LBF_EINVAL;
+namespace {
+// Objective of the state (pin, ain) of a's context; resets the gradient
+// rows and sets the adjoint to dJ/dx (buffers 0).
+lbf_status adj_seed_at(lbf_adj* a, int objective, const void* pin, const void* ain, double* J) {
   lbf_ctx* c = a->c;
   if (objective != LBF_OBJ_FROZEN_FRACTION && objective != LBF_OBJ_FRONT)
     return fail(c, LBF_EINVAL, "unknown objective");
-  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
-  const void* pin = pop_ptr(c, c->cur);
-  const void* ain = aux_ptr(c, c->cur);
   ADJCHK(adj_pass(a, 0, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
   ADJCHK(adj_pass(a, 4, pin, ain, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0));
   ADJCHK(adj_reduce(a, adj_opart(a), 2, a->lay.cblocks, adj_obj(a)));
   double AB[2];
-  HIPCHK(c, hipMemcpyAsync(AB, adj_obj(a), sizeof AB, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  HIPCHK(c, hipMemcpyAsync(AB, adj_obj(a), sizeof AB, hipMemcpyDeviceToHost, a->stream), "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(a->stream), "hipStreamSynchronize");
   if (objective == LBF_OBJ_FROZEN_FRACTION && !(AB[1] > 0.0))
     return fail(c, LBF_EINVAL, "no freezing material in the state (sum psi = 0)");
   // J = A / D: frozen fraction D = sum psi, front position D = cells per
@@ -581,7 +585,7 @@ lbf_status lbf_adjoint_seed_objective(lbf_adj* a, int objective, double* J) {
   const double D = objective == LBF_OBJ_FRONT ? double(c->kp.area) : AB[1];
   const double shift = objective == LBF_OBJ_FRONT ? 0.0 : AB[0] / D;
   const int nz = a->lay.nblocks * lbf::NPAR;
-  hipLaunchKernelGGL(adj_zero_kernel, dim3((nz + 255) / 256), dim3(256), 0, c->stream, adj_part(a), nz);
+  hipLaunchKernelGGL(adj_zero_kernel, dim3((nz + 255) / 256), dim3(256), 0, a->stream, adj_part(a), nz);
   HIPCHK(c, hipGetLastError(), "adjoint zero");
   ADJCHK(adj_pass(a, 5, pin, ain, nullptr, nullptr, nullptr, nullptr, shift, 1.0 / D));
   ADJCHK(adj_pass(a, 3, pin, ain, nullptr, nullptr, adj_lp(a, 0), adj_la(a, 0), 0.0, 0.0));
@@ -590,6 +594,16 @@ lbf_status lbf_adjoint_seed_objective(lbf_adj* a, int objective, double* J) {
   a->J = AB[0] / D;
   if (J) *J = a->J;
   return LBF_OK;
+}
+}  // namespace
+
+lbf_status lbf_adjoint_seed(lbf_adj* a, double* J) { return lbf_adjoint_seed_objective(a, LBF_OBJ_FROZEN_FRACTION, J); }
+
+lbf_status lbf_adjoint_seed_objective(lbf_adj* a, int objective, double* J) {
+  if (!a) return LBF_EINVAL;
+  lbf_ctx* c = a->c;
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  return adj_seed_at(a, objective, pop_ptr(c, c->cur), aux_ptr(c, c->cur), J);
 }
 
 lbf_status lbf_adjoint_step(lbf_adj* a, const void* state, const void* next) {
@@ -625,9 +639,9 @@ lbf_status lbf_adjoint_gradient(lbf_adj* a, double* grad) {
   if (!grad) return fail(c, LBF_EINVAL, "grad is NULL");
   if (!a->seeded) return fail(c, LBF_ESTATE, "lbf_adjoint_seed has not been called");
   ADJCHK(adj_reduce(a, adj_part(a), lbf::NPAR, a->lay.nblocks, adj_acc(a)));
-  HIPCHK(c, hipMemcpyAsync(grad, adj_acc(a), lbf::NPAR * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+  HIPCHK(c, hipMemcpyAsync(grad, adj_acc(a), lbf::NPAR * sizeof(double), hipMemcpyDeviceToHost, a->stream),
          "hipMemcpyAsync");
-  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  HIPCHK(c, hipStreamSynchronize(a->stream), "hipStreamSynchronize");
   return LBF_OK;
 }
 
@@ -712,6 +726,8 @@ void batch_table(const lbf_batch_group& g, int v, std::vector<lbf::BatchCase<S>>
     lbf_ctx* c = g.ctx[k];
     lbf::BatchCase<S>& b = t[k];
     b.P = kp_ptr(c);
+    b.soff = g.soff[k];
+    b.pop_bytes = (long long)c->lay.pop_bytes;
     for (int j = 0; j < 2; ++j) {
       b.pop[j] = static_cast<S*>(pop_ptr(c, j));
       b.aux[j] = static_cast<S*>(aux_ptr(c, j));
@@ -750,16 +766,18 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
 }
 
 // One batched step of every group at the given parity (the state buffers
-// read are cur0 ^ parity).
-lbf_status batch_launch(lbf_batch* b, int parity) {
+// read are cur0 ^ parity), or from packed batch state src to dst.
+lbf_status batch_launch(lbf_batch* b, int parity, const void* src = nullptr, void* dst = nullptr) {
   lbf_ctx* c0 = b->first;
   for (int gi = 0; gi < lbf::MAXP; ++gi) {
     lbf_batch_group& g = b->g[gi];
     if (g.ctx.empty()) continue;
     const lbf::Ops* ops = g.ctx[0]->ops;
     const int n = (int)g.ctx.size();
-    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, b->stream), "batched moments");
-    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, b->stream), "batched collide");
+    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, src, dst, b->stream),
+           "batched moments");
+    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, src, dst, b->stream),
+           "batched collide");
   }
   return LBF_OK;
 }
@@ -821,17 +839,23 @@ lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t b
   lbf_batch* b = new (std::nothrow) lbf_batch();
   if (!b) return LBF_ENOMEM;
   b->first = ctxs[0];
+  b->ncase = n;
   b->base = static_cast<char*>(dev_buf);
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->parity = 0;
   b->graph = nullptr;
   b->exec = nullptr;
   b->graph_parity = 0;
+  size_t so = 0;
   for (int k = 0; k < n; ++k) {
     lbf_batch_group& g = b->g[ctxs[k]->N - 1];
     g.ctx.push_back(ctxs[k]);
     g.cur0.push_back(ctxs[k]->cur);
+    g.user.push_back(k);
+    g.soff.push_back((long long)so);
+    so += lbf::align256(ctxs[k]->lay.pop_bytes + ctxs[k]->lay.aux_bytes);
   }
+  b->state_bytes = so;
   size_t o = 0;
   for (int gi = 0; gi < lbf::MAXP; ++gi) {
     lbf_batch_group& g = b->g[gi];
@@ -890,8 +914,10 @@ lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile) {
       hipError_t e = hipSuccess;
       for (int rep = 0; rep <= trial_steps && e == hipSuccess; ++rep) {
         if (rep == 1) e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess) e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, b->stream);
-        if (e == hipSuccess) e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, b->stream);
+        if (e == hipSuccess)
+          e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, nullptr, nullptr, b->stream);
+        if (e == hipSuccess)
+          e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, nullptr, nullptr, b->stream);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -970,6 +996,262 @@ lbf_status lbf_batch_destroy(lbf_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   delete b;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_state_bytes(const lbf_batch* b, size_t* bytes) {
+  if (!b || !bytes) return LBF_EINVAL;
+  *bytes = b->state_bytes;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_state_to_device(lbf_batch* b, void* dst) {
+  if (!b) return LBF_EINVAL;
+  lbf_ctx* c0 = b->first;
+  if (!dst || (reinterpret_cast<uintptr_t>(dst) & 255))
+    return fail(c0, LBF_EINVAL, "dst must be a 256-byte aligned device buffer");
+  ADJCHK(batch_check_members(b));
+  char* d = static_cast<char*>(dst);
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    for (size_t k = 0; k < g.ctx.size(); ++k) {
+      lbf_ctx* c = g.ctx[k];
+      const int cur = g.cur0[k] ^ b->parity;
+      HIPCHK(c0, hipMemcpyAsync(d + g.soff[k], pop_ptr(c, cur), c->lay.pop_bytes, hipMemcpyDeviceToDevice, b->stream),
+             "hipMemcpyAsync");
+      HIPCHK(c0, hipMemcpyAsync(d + g.soff[k] + c->lay.pop_bytes, aux_ptr(c, cur), c->lay.aux_bytes,
+                                hipMemcpyDeviceToDevice, b->stream),
+             "hipMemcpyAsync");
+    }
+  }
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_step_states(lbf_batch* b, const void* src, void* dst) {
+  if (!b) return LBF_EINVAL;
+  lbf_ctx* c0 = b->first;
+  if (!src || !dst || src == dst) return fail(c0, LBF_EINVAL, "src and dst must be distinct packed batch states");
+  if ((reinterpret_cast<uintptr_t>(src) & 255) || (reinterpret_cast<uintptr_t>(dst) & 255))
+    return fail(c0, LBF_EINVAL, "packed batch states must be 256-byte aligned");
+  return batch_launch(b, 0, src, dst);
+}
+
+}  // extern "C"
+
+// ----- batched reverse step ---------------------------------------------
+// Every case keeps a single-case adjoint context (its own adjoint buffer, on
+// the batch's stream); the per-step passes run as one launch per phase
+// count over the case tables, the seed, the start term and the gradient
+// reduction (once per sweep) case by case.
+struct lbf_batch_adj {
+  lbf_batch* b;
+  char* base;
+  std::vector<lbf_adj*> adj;  // caller order
+  struct Group {
+    size_t off;  // case table offset in the device buffer
+    int n, cblocks, tblocks;
+  } g[lbf::MAXP];
+  int cur;
+  bool seeded;
+};
+
+namespace {
+
+size_t batch_adj_table_bytes(int n) { return lbf::align256((size_t)n * sizeof(lbf::BatchAdjCase)); }
+
+// Buffer layout: per group a case table, then each case's adjoint buffer in
+// caller order.  Returns the total; fills the offsets if given.
+size_t batch_adj_layout(const lbf_batch* b, size_t* table_off, std::vector<size_t>* case_off) {
+  size_t o = 0;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    if (table_off) table_off[gi] = o;
+    if (!b->g[gi].ctx.empty()) o += batch_adj_table_bytes((int)b->g[gi].ctx.size());
+  }
+  std::vector<const lbf_ctx*> byuser(b->ncase, nullptr);
+  for (int gi = 0; gi < lbf::MAXP; ++gi)
+    for (size_t k = 0; k < b->g[gi].ctx.size(); ++k) byuser[b->g[gi].user[k]] = b->g[gi].ctx[k];
+  if (case_off) case_off->assign(b->ncase, 0);
+  for (int u = 0; u < b->ncase; ++u) {
+    if (case_off) (*case_off)[u] = o;
+    o += lbf::align256(lbf::make_adj_layout(&byuser[u]->prm, byuser[u]->lay).total);
+  }
+  return o;
+}
+
+void batch_adj_free(lbf_batch_adj* ba) {
+  for (lbf_adj* a : ba->adj) delete a;
+  delete ba;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbf_status lbf_batch_adjoint_bytes(const lbf_batch* b, size_t* bytes) {
+  if (!b || !bytes) return LBF_EINVAL;
+  for (int gi = 0; gi < lbf::MAXP; ++gi)
+    for (lbf_ctx* c : b->g[gi].ctx)
+      if (!c->ops->batch_adjoint) return LBF_ENOTSUP;
+  *bytes = batch_adj_layout(b, nullptr, nullptr);
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, lbf_batch_adj** out) {
+  if (!b || !out) return LBF_EINVAL;
+  *out = nullptr;
+  lbf_ctx* c0 = b->first;
+  size_t need = 0;
+  if (lbf_batch_adjoint_bytes(b, &need) != LBF_OK)
+    return fail(c0, LBF_ENOTSUP, "the batched reverse step is built for 2D float32 and float64");
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 255) || bytes < need)
+    return fail(c0, LBF_EINVAL, "batched adjoint buffer missing, unaligned or smaller than lbf_batch_adjoint_bytes");
+  lbf_batch_adj* ba = new (std::nothrow) lbf_batch_adj();
+  if (!ba) return LBF_ENOMEM;
+  ba->b = b;
+  ba->base = static_cast<char*>(dev_buf);
+  ba->cur = 0;
+  ba->seeded = false;
+  size_t toff[lbf::MAXP];
+  std::vector<size_t> coff;
+  batch_adj_layout(b, toff, &coff);
+  ba->adj.assign(b->ncase, nullptr);
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    lbf_batch_adj::Group& G = ba->g[gi];
+    G.off = toff[gi];
+    G.n = (int)g.ctx.size();
+    G.cblocks = G.tblocks = 0;
+    if (g.ctx.empty()) continue;
+    std::vector<lbf::BatchAdjCase> t(g.ctx.size());
+    for (size_t k = 0; k < g.ctx.size(); ++k) {
+      lbf_ctx* c = g.ctx[k];
+      lbf_adj* a = new (std::nothrow) lbf_adj();
+      if (!a) {
+        batch_adj_free(ba);
+        return LBF_ENOMEM;
+      }
+      a->c = c;
+      a->lay = lbf::make_adj_layout(&c->prm, c->lay);
+      a->base = ba->base + coff[g.user[k]];
+      a->stream = b->stream;
+      a->cur = 0;
+      a->seeded = false;
+      a->J = 0.0;
+      ba->adj[g.user[k]] = a;
+      lbf::BatchAdjCase& bc = t[k];
+      bc.P = kp_ptr(c);
+      bc.soff = g.soff[k];
+      bc.pop_bytes = (long long)c->lay.pop_bytes;
+      for (int j = 0; j < 2; ++j) {
+        bc.lp[j] = adj_lp(a, j);
+        bc.la[j] = adj_la(a, j);
+      }
+      bc.work = adj_work(a);
+      bc.part = adj_part(a);
+      // the single-case grids: one thread per cell for the collide reverse,
+      // the step geometry for the tiled gather
+      bc.cblocks = a->lay.cblocks;
+      bc.first_cblock = G.cblocks;
+      G.cblocks += bc.cblocks;
+      const lbf::Geometry geo = c->prm.precision == LBF_FP64
+                                    ? lbf::step_geometry<lbf::CfgOf<2, 1, double, double>>(c->kp)
+                                    : lbf::step_geometry<lbf::CfgOf<2, 1, float, float>>(c->kp);
+      bc.ntx = geo.ntx;
+      bc.nty = geo.nty;
+      bc.chunk = geo.chunk;
+      bc.nblocks = geo.nblocks;
+      bc.first_tblock = G.tblocks;
+      G.tblocks += bc.nblocks;
+    }
+    HIPCHK(c0, hipMemcpyAsync(ba->base + G.off, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
+           "hipMemcpyAsync");
+    HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  }
+  *out = ba;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_adjoint_seed(lbf_batch_adj* ba, int objective, const void* state, double* J) {
+  if (!ba) return LBF_EINVAL;
+  lbf_batch* b = ba->b;
+  if (!state) return fail(b->first, LBF_EINVAL, "state is NULL");
+  const char* st = static_cast<const char*>(state);
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    for (size_t k = 0; k < g.ctx.size(); ++k) {
+      lbf_adj* a = ba->adj[g.user[k]];
+      const char* pin = st + g.soff[k];
+      double Jk = 0.0;
+      const lbf_status s = adj_seed_at(a, objective, pin, pin + g.ctx[k]->lay.pop_bytes, &Jk);
+      if (s != LBF_OK) {
+        if (s != LBF_EDEVICE) fail(b->first, s, g.ctx[k]->err);
+        return s;
+      }
+      if (J) J[g.user[k]] = Jk;
+    }
+  }
+  ba->cur = 0;
+  ba->seeded = true;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_adjoint_step(lbf_batch_adj* ba, const void* state, const void* next) {
+  if (!ba) return LBF_EINVAL;
+  lbf_batch* b = ba->b;
+  lbf_ctx* c0 = b->first;
+  if (!ba->seeded) return fail(c0, LBF_ESTATE, "lbf_batch_adjoint_seed has not been called");
+  if (!state || !next) return fail(c0, LBF_EINVAL, "state and next must be packed batch states");
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    const lbf_batch_adj::Group& G = ba->g[gi];
+    if (!G.n) continue;
+    const lbf::Ops* ops = b->g[gi].ctx[0]->ops;
+    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, G.cblocks, state, next, ba->cur, b->stream),
+           "batched collide reverse");
+    HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, b->stream),
+           "batched gather");
+  }
+  ba->cur ^= 1;
+  for (lbf_adj* a : ba->adj) a->cur = ba->cur;
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_adjoint_finish(lbf_batch_adj* ba, const void* state0) {
+  if (!ba) return LBF_EINVAL;
+  lbf_batch* b = ba->b;
+  if (!ba->seeded) return fail(b->first, LBF_ESTATE, "lbf_batch_adjoint_seed has not been called");
+  if (!state0) return fail(b->first, LBF_EINVAL, "state0 is NULL");
+  const char* st = static_cast<const char*>(state0);
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    for (size_t k = 0; k < g.ctx.size(); ++k) {
+      lbf_adj* a = ba->adj[g.user[k]];
+      const char* pin = st + g.soff[k];
+      ADJCHK(adj_pass(a, 6, pin, pin + g.ctx[k]->lay.pop_bytes, adj_lp(a, a->cur), adj_la(a, a->cur), nullptr,
+                      nullptr, 0.0, 0.0));
+    }
+  }
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_adjoint_gradient(lbf_batch_adj* ba, double* grad) {
+  if (!ba) return LBF_EINVAL;
+  lbf_batch* b = ba->b;
+  lbf_ctx* c0 = b->first;
+  if (!grad) return fail(c0, LBF_EINVAL, "grad is NULL");
+  if (!ba->seeded) return fail(c0, LBF_ESTATE, "lbf_batch_adjoint_seed has not been called");
+  for (int u = 0; u < b->ncase; ++u) {
+    lbf_adj* a = ba->adj[u];
+    ADJCHK(adj_reduce(a, adj_part(a), lbf::NPAR, a->lay.nblocks, adj_acc(a)));
+    HIPCHK(c0, hipMemcpyAsync(grad + (size_t)u * lbf::NPAR, adj_acc(a), lbf::NPAR * sizeof(double),
+                              hipMemcpyDeviceToHost, b->stream),
+           "hipMemcpyAsync");
+  }
+  HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  return LBF_OK;
+}
+
+lbf_status lbf_batch_adjoint_destroy(lbf_batch_adj* ba) {
+  if (ba) batch_adj_free(ba);
   return LBF_OK;
 }
 

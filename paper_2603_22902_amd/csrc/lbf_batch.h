@@ -14,11 +14,14 @@
 namespace lbf {
 
 // One case of a batch.  Buffer cur holds the state at even batch steps.
+// soff, pop_bytes: where the case's state sits in a packed batch state (all
+// cases' device states, each laid out as lbf_state_to_device writes it).
 template <typename S>
 struct BatchCase {
   const KParams* P;  // device copy of the case's parameter block
   S* pop[2];
   S* aux[2];
+  long long soff, pop_bytes;
   int cur;
   int ntx, nty, chunk, nblocks;  // collide-pass geometry of this case
   int mblocks;                   // moments-pass blocks of this case
@@ -48,26 +51,43 @@ __device__ inline void load_params(KParams& dst, const KParams* src) {
   __syncthreads();
 }
 
-template <class C>
+// Pointers of a case's step: its own buffers at the given parity, or
+// (PACKED) the case's slice of the packed batch states src -> dst.
+template <typename S, bool PACKED>
+__device__ inline void batch_io(const BatchCase<S>& bc, int parity, const char* src, char* dst, StepArgs<S>& a) {
+  if constexpr (PACKED) {
+    a.pin = reinterpret_cast<const S*>(src + bc.soff);
+    a.ain = reinterpret_cast<const S*>(src + bc.soff + bc.pop_bytes);
+    a.pout = reinterpret_cast<S*>(dst + bc.soff);
+    a.aout = reinterpret_cast<S*>(dst + bc.soff + bc.pop_bytes);
+  } else {
+    const int in = bc.cur ^ parity;
+    a.pin = bc.pop[in];
+    a.pout = bc.pop[1 - in];
+    a.ain = bc.aux[in];
+    a.aout = bc.aux[1 - in];
+  }
+}
+
+template <class C, bool PACKED>
 __global__ void __launch_bounds__(MOMENT_THREADS)
-    batch_moment_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int parity) {
+    batch_moment_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int parity,
+                        const char* __restrict__ src, char* __restrict__ dst) {
   using S = typename C::S;
   __shared__ KParams P;
   const int k = batch_case<S>(cs, ncase, blockIdx.x, false);
   const BatchCase<S>& bc = cs[k];
   load_params(P, bc.P);
-  const int in = bc.cur ^ parity;
   StepArgs<S> a;
-  a.pin = bc.pop[in];
-  a.ain = bc.aux[in];
-  a.aout = bc.aux[1 - in];
+  batch_io<S, PACKED>(bc, parity, src, dst, a);
   const int cell = (blockIdx.x - bc.first_mblock) * MOMENT_THREADS + threadIdx.x;
   if (cell < P.ncell) moment_cell<C>(a, P, cell);
 }
 
-template <class C>
+template <class C, bool PACKED>
 __global__ void __launch_bounds__(C::NT)
-    batch_collide_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nblocks, int parity) {
+    batch_collide_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nblocks, int parity,
+                         const char* __restrict__ src, char* __restrict__ dst) {
   using S = typename C::S;
   __shared__ KParams P;
   __shared__ Smem<C> sm;
@@ -75,12 +95,8 @@ __global__ void __launch_bounds__(C::NT)
   const int k = batch_case<S>(cs, ncase, Lg, true);
   const BatchCase<S>& bc = cs[k];
   load_params(P, bc.P);
-  const int in = bc.cur ^ parity;
   StepArgs<S> a;
-  a.pin = bc.pop[in];
-  a.pout = bc.pop[1 - in];
-  a.ain = bc.aux[in];
-  a.aout = bc.aux[1 - in];
+  batch_io<S, PACKED>(bc, parity, src, dst, a);
   a.mom = a.aout;
   a.mout = nullptr;
   a.mfield = 0;
@@ -125,32 +141,44 @@ inline void batch_geometry(const KParams& P, int tx, long long target, int& ntx,
   nblocks = (int)((long long)ntx * ((P.nwn + chunk - 1) / chunk));
 }
 
-// pass 0: moments, 1: collide; variant indexes BATCH_TILES.
-template <int NP, typename S, typename R>
-inline hipError_t launch_batch(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
-                               hipStream_t s) {
-  const auto* cs = static_cast<const BatchCase<S>*>(cases);
+template <int NP, typename S, typename R, bool PACKED>
+inline hipError_t launch_batch_t(int pass, int variant, const BatchCase<S>* cs, int ncase, int nblocks, int parity,
+                                 const char* src, char* dst, hipStream_t s) {
   if (pass == 0) {
-    hipLaunchKernelGGL((batch_moment_kernel<Cfg<2, NP, S, R, 128, 1>>), dim3(nblocks), dim3(MOMENT_THREADS), 0, s,
-                       cs, ncase, parity);
+    hipLaunchKernelGGL((batch_moment_kernel<Cfg<2, NP, S, R, 128, 1>, PACKED>), dim3(nblocks), dim3(MOMENT_THREADS),
+                       0, s, cs, ncase, parity, src, dst);
     return hipGetLastError();
   }
   switch (variant) {
     case 0:
-      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 64, 1>>), dim3(nblocks), dim3(64), 0, s, cs, ncase,
-                         nblocks, parity);
+      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 64, 1>, PACKED>), dim3(nblocks), dim3(64), 0, s, cs,
+                         ncase, nblocks, parity, src, dst);
       break;
     case 1:
-      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 128, 1>>), dim3(nblocks), dim3(128), 0, s, cs,
-                         ncase, nblocks, parity);
+      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 128, 1>, PACKED>), dim3(nblocks), dim3(128), 0, s,
+                         cs, ncase, nblocks, parity, src, dst);
       break;
     case 2:
-      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 256, 1>>), dim3(nblocks), dim3(256), 0, s, cs,
-                         ncase, nblocks, parity);
+      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 256, 1>, PACKED>), dim3(nblocks), dim3(256), 0, s,
+                         cs, ncase, nblocks, parity, src, dst);
       break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// pass 0: moments, 1: collide; variant indexes BATCH_TILES.  With src and
+// dst (packed batch states) the step reads src and writes dst instead of
+// the cases' own buffers.
+template <int NP, typename S, typename R>
+inline hipError_t launch_batch(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
+                               const void* src, void* dst, hipStream_t s) {
+  const auto* cs = static_cast<const BatchCase<S>*>(cases);
+  if (src && dst)
+    return launch_batch_t<NP, S, R, true>(pass, variant, cs, ncase, nblocks, parity, static_cast<const char*>(src),
+                                          static_cast<char*>(dst), s);
+  if (src || dst) return hipErrorInvalidValue;
+  return launch_batch_t<NP, S, R, false>(pass, variant, cs, ncase, nblocks, parity, nullptr, nullptr, s);
 }
 
 }  // namespace lbf

@@ -1,0 +1,120 @@
+// Batched reverse step: the two per-step passes of the reverse step (collide
+// reverse, tiled gather) for many 2D cases of one phase count, one launch
+// each.  A block finds its case in the case table (binary search over the
+// cases' first block numbers), copies the case's parameter block into LDS and
+// runs the single-case phase functions.  Each case keeps the block
+// decomposition and the gradient rows of its single-case reverse step, so its
+// gradient is bitwise the one a single-case sweep gives.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbf_adjoint_kernels.h"
+#include "lbf_batch.h"
+
+namespace lbf {
+
+// One case of a batched reverse step.  The states x^n and x^{n+1} of a step
+// are packed batch states (soff, pop_bytes as in BatchCase); the adjoint
+// buffers are the case's own (layout of the single-case reverse step).
+struct BatchAdjCase {
+  const KParams* P;
+  long long soff, pop_bytes;
+  void* lp[2];
+  void* la[2];
+  void* work;
+  double* part;                       // gradient rows of the case
+  int cblocks, first_cblock;          // collide reverse: ceil(ncell / 256) blocks
+  int ntx, nty, chunk, nblocks;       // tiled gather geometry (single-case step geometry)
+  int first_tblock;
+};
+
+// Last case k with first[k] <= b (uniform across the block).
+__device__ inline int batch_adj_case(const BatchAdjCase* cs, int ncase, int b, bool collide) {
+  int lo = 0, hi = ncase - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int f = collide ? cs[mid].first_cblock : cs[mid].first_tblock;
+    if (f <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Arguments of a case's reverse step through x^n = state (its moments from
+// x^{n+1} = next); the adjoint of x^{n+1} is in buffers `parity`.
+template <class C>
+__device__ inline AdjArgs<C> batch_adj_args(const BatchAdjCase& bc, const char* state, const char* next,
+                                            int parity) {
+  using S = typename C::S;
+  AdjArgs<C> a;
+  a.pin = reinterpret_cast<const S*>(state + bc.soff);
+  a.ain = reinterpret_cast<const S*>(state + bc.soff + bc.pop_bytes);
+  a.mom = reinterpret_cast<const S*>(next + bc.soff + bc.pop_bytes);
+  a.lpin = static_cast<const S*>(bc.lp[parity]);
+  a.lain = static_cast<const S*>(bc.la[parity]);
+  a.lpout = static_cast<S*>(bc.lp[1 - parity]);
+  a.laout = static_cast<S*>(bc.la[1 - parity]);
+  a.work = static_cast<typename C::R*>(bc.work);
+  return a;
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+    batch_adj_collide_kernel(const BatchAdjCase* __restrict__ cs, int ncase, const char* __restrict__ state,
+                             const char* __restrict__ next, int parity) {
+  __shared__ KParams P;
+  const BatchAdjCase& bc = cs[batch_adj_case(cs, ncase, blockIdx.x, true)];
+  load_params(P, bc.P);
+  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  const int lb = blockIdx.x - bc.first_cblock;
+  const int cell = lb * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
+  block_sum_to<NPAR, true>(g, bc.part + (long long)lb * NPAR);
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
+    batch_adj_gather_kernel(const BatchAdjCase* __restrict__ cs, int ncase, int nblocks,
+                            const char* __restrict__ state, const char* __restrict__ next, int parity) {
+  __shared__ KParams P;
+  __shared__ FdaRing<C> ring;
+  const int Lg = xcd_remap(blockIdx.x, nblocks);
+  const BatchAdjCase& bc = cs[batch_adj_case(cs, ncase, Lg, false)];
+  load_params(P, bc.P);
+  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
+  StepArgs<typename C::S> sa;
+  sa.ntx = bc.ntx;
+  sa.nty = bc.nty;
+  sa.chunk = bc.chunk;
+  sa.nblocks = bc.nblocks;
+  const int t = Lg - bc.first_tblock;
+  gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, bc.part + (long long)t * NPAR);
+}
+
+// pass 0: collide reverse over cblocks blocks, 1: tiled gather over nblocks.
+template <int NP, typename S, typename R>
+inline hipError_t launch_batch_adjoint(int pass, const void* cases, int ncase, int nblocks, const void* state,
+                                       const void* next, int parity, hipStream_t s) {
+  using C = CfgOf<2, NP, S, R>;
+  const auto* cs = static_cast<const BatchAdjCase*>(cases);
+  const char* st = static_cast<const char*>(state);
+  const char* nx = static_cast<const char*>(next);
+  if (!st || !nx || nblocks < 1) return hipErrorInvalidValue;
+  if (pass == 0)
+    hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(ADJ_THREADS), 0, s, cs, ncase, st, nx,
+                       parity);
+  else if (pass == 1)
+    hipLaunchKernelGGL((batch_adj_gather_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, ncase, nblocks, st, nx,
+                       parity);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace lbf

@@ -3,6 +3,7 @@
 // float64).
 #include "lbf_adjoint_kernels.h"
 #include "lbf_batch.h"
+#include "lbf_batch_adjoint.h"
 #include "lbf_kernels.h"
 #include "lbf_ops.h"
 

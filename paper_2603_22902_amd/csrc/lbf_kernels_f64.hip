@@ -2,6 +2,7 @@
 // contraction so that each operation rounds as written.
 #include "lbf_adjoint_kernels.h"
 #include "lbf_batch.h"
+#include "lbf_batch_adjoint.h"
 #include "lbf_kernels.h"
 #include "lbf_ops.h"
 

@@ -2,6 +2,7 @@
 // path with the rounding of float64 arithmetic inside each step.
 #include "lbf_adjoint_kernels.h"
 #include "lbf_batch.h"
+#include "lbf_batch_adjoint.h"
 #include "lbf_kernels.h"
 #include "lbf_ops.h"
 

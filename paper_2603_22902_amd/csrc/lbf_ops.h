@@ -27,9 +27,14 @@ struct Ops {
                         void* lpout, void* laout, const void* mom, void* work, const KParams& P,
                         const KParams* dP, double* part, double A, double B, hipStream_t s);
   // Batched passes over a case table (lbf_batch.h), 2D only (NULL in 3D):
-  // pass 0 moments, 1 collide with row tile BATCH_TILES[variant].
+  // pass 0 moments, 1 collide with row tile BATCH_TILES[variant]; with src
+  // and dst (packed batch states) from src to dst, else the cases' buffers.
   hipError_t (*batch)(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
-                      hipStream_t s);
+                      const void* src, void* dst, hipStream_t s);
+  // Batched reverse-step passes (lbf_batch_adjoint.h): pass 0 collide
+  // reverse, 1 tiled gather; NULL where the adjoint is not built.
+  hipError_t (*batch_adjoint)(int pass, const void* cases, int ncase, int nblocks, const void* state,
+                              const void* next, int parity, hipStream_t s);
 };
 
 // dim 2 or 3, nphase 1..4; NULL if not built.  f32: float32 storage and
@@ -86,15 +91,26 @@ const Ops* ops_mix(int dim, int nphase);
         return hipErrorNotSupported;                                                             \
     }                                                                                            \
     static hipError_t batch(int pass, int variant, const void* cases, int ncase, int nblocks,    \
-                            int parity, hipStream_t s) {                                         \
+                            int parity, const void* src, void* dst, hipStream_t s) {             \
       if constexpr (DIM == 2)                                                                    \
-        return launch_batch<NP, ST, RT>(pass, variant, cases, ncase, nblocks, parity, s);        \
+        return launch_batch<NP, ST, RT>(pass, variant, cases, ncase, nblocks, parity, src, dst,  \
+                                        s);                                                      \
+      else                                                                                       \
+        return hipErrorNotSupported;                                                             \
+    }                                                                                            \
+    static hipError_t batch_adjoint(int pass, const void* cases, int ncase, int nblocks,         \
+                                    const void* state, const void* next, int parity,             \
+                                    hipStream_t s) {                                             \
+      if constexpr (ADJ && DIM == 2)                                                             \
+        return launch_batch_adjoint<NP, ST, RT>(pass, cases, ncase, nblocks, state, next,        \
+                                                parity, s);                                      \
       else                                                                                       \
         return hipErrorNotSupported;                                                             \
     }                                                                                            \
     static constexpr Ops ops = {&step, &init, &diag, &widen,                                     \
                                 (ADJ && DIM == 2) ? &adjoint : nullptr,                          \
-                                DIM == 2 ? &batch : nullptr};                                    \
+                                DIM == 2 ? &batch : nullptr,                                     \
+                                (ADJ && DIM == 2) ? &batch_adjoint : nullptr};                   \
   };                                                                                             \
   const Ops* NAME(int dim, int nphase) {                                                         \
     static const Ops* table[2][4] = {                                                            \

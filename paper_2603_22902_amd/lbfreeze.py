@@ -86,6 +86,16 @@ def lib():
         L.lbf_batch_capture.argtypes = [vp]
         L.lbf_batch_replay.argtypes = [vp, ctypes.c_int]
         L.lbf_batch_destroy.argtypes = [vp]
+        L.lbf_batch_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbf_batch_state_to_device.argtypes = [vp, vp]
+        L.lbf_batch_step_states.argtypes = [vp, vp, vp]
+        L.lbf_batch_adjoint_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbf_batch_adjoint_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.lbf_batch_adjoint_seed.argtypes = [vp, ctypes.c_int, vp, _PD]
+        L.lbf_batch_adjoint_step.argtypes = [vp, vp, vp]
+        L.lbf_batch_adjoint_finish.argtypes = [vp, vp]
+        L.lbf_batch_adjoint_gradient.argtypes = [vp, _PD]
+        L.lbf_batch_adjoint_destroy.argtypes = [vp]
         L.lbf_get_moments.argtypes = [vp, ctypes.c_uint, _PD]
         L.lbf_get_populations.argtypes = [vp, _PD]
         L.lbf_get_aux.argtypes = [vp, _PD]
@@ -107,7 +117,11 @@ def lib():
                      "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_seed_objective", "lbf_adjoint_step", "lbf_adjoint_finish",
                      "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy",
                      "lbf_batch_bytes", "lbf_batch_create", "lbf_batch_set_tiles", "lbf_batch_tune",
-                     "lbf_batch_step", "lbf_batch_capture", "lbf_batch_replay", "lbf_batch_destroy"):
+                     "lbf_batch_step", "lbf_batch_capture", "lbf_batch_replay", "lbf_batch_destroy",
+                     "lbf_batch_state_bytes", "lbf_batch_state_to_device", "lbf_batch_step_states",
+                     "lbf_batch_adjoint_bytes", "lbf_batch_adjoint_create", "lbf_batch_adjoint_seed",
+                     "lbf_batch_adjoint_step", "lbf_batch_adjoint_finish", "lbf_batch_adjoint_gradient",
+                     "lbf_batch_adjoint_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

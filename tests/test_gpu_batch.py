@@ -1,7 +1,9 @@
 """GPU batched cases (lbf_batch_* through the C ABI): a batch of uneven 2D
 cases gives bitwise the states of stepping each solver alone, eagerly and
 from every replay of the captured graph; the autotuner leaves the states
-unchanged."""
+unchanged; batched steps between packed states and the batched reverse
+sweep give bitwise each case's single-case states, objective and
+gradient."""
 import numpy as np
 import pytest
 
@@ -86,3 +88,83 @@ def test_member_stepped_alone_is_refused():
     with pytest.raises(LbfError) as e:
         b.step(1)
     assert e.value.status == LBF_ESTATE
+
+
+def _packed_offsets(solvers):
+    out, o = [], 0
+    for s in solvers:
+        out.append(o)
+        o += (s.state_device_bytes() + 255) // 256 * 256
+    return out, o
+
+
+def test_packed_step_states_equal_single_case():
+    """lbf_batch_step_states from a packed state equals lbf_step_states of
+    every case on its own, bitwise, and leaves the members untouched."""
+    import torch
+
+    from paper_2603_22902_amd.batch import Batch
+    cases = _cases()
+    got = _solvers(cases)
+    b = Batch(got)
+    b.set_tiles({2: 256, 3: 64})
+    offs, total = _packed_offsets(got)
+    assert b.state_bytes() == total
+    x = b.states(2)
+    b.state_to_device(x[0])
+    b.step_states(x[0], x[1])
+    b.synchronize()
+    for s, o in zip(got, offs):
+        nb = s.state_device_bytes()
+        one = torch.empty((2, nb), dtype=torch.uint8, device=s.device)
+        s.lbf_state_to_device(one[0])
+        s.lbf_step_states(one[0], one[1])
+        torch.cuda.synchronize()
+        assert torch.equal(x[0, o:o + nb], one[0])
+        assert torch.equal(x[1, o:o + nb], one[1])
+        assert s.step_count() == 0
+
+
+def _adj_cases(precision):
+    cs = synth.batch(n_cases=5, seed_k=11, sizes=(64, 128), precision=precision)
+    return [synth.near_melting(c) for c in cs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("objective", ["frozen_fraction", "front"])
+def test_batched_adjoint_equals_single_case_sweeps(precision, objective):
+    """The batched sweep (checkpoints and tape as packed states, batched
+    recomputation and reverse steps) gives every case bitwise the objective
+    and gradient of its single-case sweep."""
+    from paper_2603_22902_amd.adjoint import frozen_fraction_and_gradient
+    from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
+    cases = _adj_cases(precision)
+    assert len({c["params"]["nphase"] for c in cases}) == 2
+    n, window = 12, 5
+    print("batched adjoint", precision, objective, [c["T"].shape for c in cases], flush=True)
+    got = _solvers(cases)
+    b = Batch(got)
+    b.set_tiles({2: 64, 3: 256})
+    ck = batch_forward_with_checkpoints(b, n, window)
+    J, g = batch_reverse_sweep(b, ck, n, window, objective=objective)
+    assert np.all(np.isfinite(g)) and np.any(J > 0.0)
+    for k, c in enumerate(cases):
+        Jk, gk = frozen_fraction_and_gradient(c, n, window, objective=objective)
+        assert J[k] == Jk, (k, J[k], Jk)
+        assert np.array_equal(g[k], gk["raw"]), (k, g[k], gk["raw"])
+
+
+def test_batched_adjoint_through_graph_replays():
+    """The forward pass replayed from the captured graph gives the same
+    batched gradient as eager steps."""
+    from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
+    cases = _adj_cases("fp32")
+    n, window = 12, 4
+    res = []
+    for graph in (False, True):
+        b = Batch(_solvers(cases))
+        if graph:
+            b.capture()
+        ck = batch_forward_with_checkpoints(b, n, window, graph=graph)
+        res.append(batch_reverse_sweep(b, ck, n, window))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
