@@ -163,7 +163,7 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
             "J": J, "dJ_dTw": dJ_dTw, "dJ_dSte": dJ_dSte}
 
 
-def batch_leg(nsteps: int = 200, precision: str = "fp32") -> dict:
+def batch_leg(nsteps: int = 200, precision: str = "fp32", adjoint: bool = True) -> dict:
     """The 64-case 2D sweep (sides 64..512, N 2 or 3): total-cells MLUPS of
     (a) the batch replayed from its captured graph after autotuning, (b) the
     same batch launched step by step, (c) the cases looped one by one with
@@ -209,7 +209,65 @@ def batch_leg(nsteps: int = 200, precision: str = "fp32") -> dict:
            "mlups_looped_single": mlups(t_loop),
            "speedup_graph_vs_looped": round(t_loop / t_graph, 3)}
     b.close()
+    if adjoint:
+        print(f"[bench] batch forward {out}; batched adjoint sweep next", file=sys.stderr, flush=True)
+        out["adjoint"] = batch_adjoint_leg(cases, solvers, tiles, nsteps, window=50)
     return out
+
+
+def batch_adjoint_leg(cases, solvers, tiles, nsteps: int, window: int) -> dict:
+    """Forward plus reverse sweep of every case (frozen fraction, start just
+    above melting): the batched sweep (forward from the captured graph with
+    packed checkpoints, batched recomputation and reverse steps) against the
+    same sweeps looped case by case; wall-clock seconds around each, after
+    a device synchronisation.  Both give bitwise the same gradients."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2603_22902_amd.adjoint import forward_with_checkpoints, reverse_sweep
+    from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
+
+    adj_cases = [synth.near_melting(c) for c in cases]
+    for s, c in zip(solvers, adj_cases):
+        s.init_case(c)
+    ncell = sum(s.ncell for s in solvers)
+    b = Batch(solvers)
+    b.set_tiles(tiles)
+    b.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ck = batch_forward_with_checkpoints(b, nsteps, window, graph=True)
+    b.synchronize()
+    t1 = time.perf_counter()
+    tm = {}
+    J, g = batch_reverse_sweep(b, ck, nsteps, window, timing=tm)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    del ck
+    # the same sweeps, one case at a time
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    gl = []
+    for s, c in zip(solvers, adj_cases):
+        ckk = forward_with_checkpoints(s, c, nsteps, window)
+        gl.append(reverse_sweep(s, ckk, nsteps, window)[1]["raw"])
+        del ckk
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    fwd, rev, loop = t1 - t0, t2 - t1, t4 - t3
+    return {"steps": nsteps, "window": window, "objective": "frozen_fraction",
+            "forward_s": round(fwd, 4), "reverse_sweep_s": round(rev, 4),
+            "recompute_ms": round(tm["recompute_ms"], 2), "reverse_steps_ms": round(tm["reverse_ms"], 2),
+            "ratio_adjoint_forward": round(rev / fwd, 3),
+            "mlups_forward_plus_adjoint": round(ncell * nsteps / (fwd + rev) / 1e6, 1),
+            "looped_single_s": round(loop, 4),
+            "speedup_vs_looped": round(loop / (fwd + rev), 3),
+            "gradients_bitwise_equal_looped": bool(all(np.array_equal(g[k], gl[k]) for k in range(len(gl)))),
+            "J_range": [float(J.min()), float(J.max())]}
 
 
 def main():
