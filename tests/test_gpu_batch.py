@@ -168,3 +168,38 @@ def test_batched_adjoint_through_graph_replays():
         ck = batch_forward_with_checkpoints(b, n, window, graph=graph)
         res.append(batch_reverse_sweep(b, ck, n, window))
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
+def test_batched_adjoint_argument_errors():
+    """Refusals on the host, before any launch: adjoint step before seed,
+    a missing next state, unaligned or aliased packed states, an unknown
+    objective, and a batch whose cases have no reverse step (float32
+    storage with float64 arithmetic)."""
+    import ctypes
+
+    from paper_2603_22902_amd.batch import Batch, BatchAdjoint
+    from paper_2603_22902_amd.lbfreeze import LBF_EINVAL, LBF_ENOTSUP, LBF_ESTATE, LbfError, lib
+    b = Batch(_solvers(_adj_cases("fp32")[:2]))
+    x = b.states(2)
+    b.state_to_device(x[0])
+    adj = BatchAdjoint(b)
+    with pytest.raises(LbfError) as e:
+        adj.step(x[0], x[1])
+    assert e.value.status == LBF_ESTATE
+    p0, p1 = ctypes.c_void_p(x[0].data_ptr()), ctypes.c_void_p(x[1].data_ptr())
+    with pytest.raises(ValueError):
+        adj.seed(x[0], objective="volume")
+    assert lib().lbf_batch_adjoint_seed(adj._h, 7, p0, None) == LBF_EINVAL
+    J = adj.seed(x[0])
+    assert J.shape == (2,)
+    assert lib().lbf_batch_adjoint_step(adj._h, p0, None) == LBF_EINVAL
+    assert lib().lbf_batch_step_states(b._h, ctypes.c_void_p(x[0].data_ptr() + 4), p1) == LBF_EINVAL
+    assert lib().lbf_batch_step_states(b._h, p0, p0) == LBF_EINVAL
+    assert lib().lbf_batch_state_to_device(b._h, ctypes.c_void_p(x[1].data_ptr() + 64)) == LBF_EINVAL
+    adj.close()
+    b.close()
+    bm = Batch(_solvers(_adj_cases("mixed")[:2]))
+    with pytest.raises(LbfError) as e:
+        BatchAdjoint(bm)
+    assert e.value.status == LBF_ENOTSUP
+    bm.close()
