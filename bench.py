@@ -107,7 +107,36 @@ def cpu_baseline(case, budget_s: float = 20.0) -> dict:
     return {"value": ncell * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"{steps} full step(s) of the same {ncell}-cell workload in float64 "
-                      f"({el:.1f} s, OpenMP over cells)"}
+                      f"({el:.1f} s, OpenMP over cells)",
+            "host": host_info()}
+
+
+def host_info() -> dict:
+    """The host the oracle ran on: CPU model, logical CPUs, and a triad
+    bandwidth (a = b + 3 c over 2^27 float64 per array, torch's CPU threads)
+    for the oracle's own memory roofline."""
+    import torch
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = 1 << 27
+    b = torch.ones(n, dtype=torch.float64)
+    c = torch.ones(n, dtype=torch.float64)
+    a = torch.empty(n, dtype=torch.float64)
+    torch.add(b, c, alpha=3.0, out=a)
+    best = float("inf")
+    for _ in range(3):
+        t0 = time.perf_counter()
+        torch.add(b, c, alpha=3.0, out=a)
+        best = min(best, time.perf_counter() - t0)
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "torch_threads": torch.get_num_threads(),
+            "triad_GB_s": round(3 * n * 8 / best / 1e9, 1)}
 
 
 def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) -> dict:
@@ -297,8 +326,12 @@ def main():
     s.init_case(case)
     stream = s.stream
     ncell = s.ncell
+    d0 = s.lbf_diagnostics(check_nan=False)
     s.lbf_step(args.warmup)
     torch.cuda.synchronize()
+    # per-phase mass and front position every 100 steps of the timed run
+    # (the diagnostics are part of the timed work)
+    dlog = {"interval": 100, "step": [], "front": [], "mass_drift_max_rel": []}
 
     # Timed region 1 (the metric): K steps with diagnostics every 100 steps.
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -311,7 +344,10 @@ def main():
         s.lbf_step(n)
         done += n
         if n == 100:
-            s.lbf_diagnostics(check_nan=False)
+            d = s.lbf_diagnostics(check_nan=False)
+            dlog["step"].append(args.warmup + done)
+            dlog["front"].append(d["front"])
+            dlog["mass_drift_max_rel"].append(d["mass"])
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -333,6 +369,11 @@ def main():
     ms_per_step = ms_total / args.steps
     mlups = ncell * args.steps / (ms_total * 1e-3) / 1e6
     dtype = {"fp32": "f32", "mixed": "f32 storage / f64 arithmetic", "fp64": "f64"}[args.precision]
+    m0 = d0["mass"]
+    masses = dlog.pop("mass_drift_max_rel")
+    dlog["mass_drift_rel_per_phase"] = [[round(float((m[p] - m0[p]) / m0[p]), 7) if m0[p] != 0.0 else 0.0
+                                         for p in range(len(m0))] for m in masses]
+    dlog["front_initial"] = float(d0["front"])
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -342,6 +383,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "collide_kernel", "kernel_us": round(ms_col * 1e3, 2),
                      "bytes_per_cell": bpc["collide"]},
+        "diagnostics": dlog,
         "kernels": {
             "moment_kernel": {"us": round(ms_mom * 1e3, 2), "bytes_per_cell": bpc["moments"],
                               "GB/s": round(bpc["moments"] * ncell / (ms_mom * 1e-3) / 1e9, 1)},
