@@ -149,7 +149,10 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
 
     import synth
     from paper_2603_22902_amd import Solver
-    from paper_2603_22902_amd.adjoint import forward_with_checkpoints, reverse_sweep
+    import numpy as np
+
+    from paper_2603_22902_amd.adjoint import (forward_to_tape, forward_with_checkpoints, reverse_from_tape,
+                                               reverse_sweep, tape_bytes)
 
     case = synth.near_melting(synth.compound(precision=precision))
     prm = case["params"]
@@ -174,6 +177,28 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
     e1.record(s.stream)
     torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / nsteps
+    # the whole trajectory in an HBM-resident tape (no recomputation), when
+    # it fits in half the free device memory
+    full = None
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = tape_bytes(s, nsteps)
+    if need < 0.5 * free:
+        torch.cuda.synchronize()
+        e0.record(s.stream)
+        tape = forward_to_tape(s, case, nsteps)
+        e1.record(s.stream)
+        t2 = {}
+        J2, g2 = reverse_from_tape(s, tape, nsteps, timing=t2)
+        torch.cuda.synchronize()
+        ftape = e0.elapsed_time(e1)
+        full = {"tape_GB": round(need / 1e9, 2), "forward_to_tape_ms": round(ftape, 2),
+                "reverse_ms": round(t2["reverse_ms"], 2),
+                "ratio_vs_plain_forward": round(t2["reverse_ms"] / (step_ms * nsteps), 3),
+                "ratio_vs_forward_to_tape": round(t2["reverse_ms"] / ftape, 3),
+                "gradient_bitwise_equal_checkpointed": bool(J2 == J and np.array_equal(g2["raw"], g["raw"]))}
+        del tape
+        torch.cuda.empty_cache()
     N = prm["nphase"]
     Tw, Tm = prm["T_face"][0], synth.T_MELT
     frz = [p for p in range(N) if prm["freezes"][p]]
@@ -189,7 +214,8 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
             "reverse_step_ms": round(t["reverse_ms"] / nsteps, 4),
             "forward_step_ms": round(step_ms, 4),
             "ratio_no_recompute": round(t["reverse_ms"] / nsteps / step_ms, 3),
-            "J": J, "dJ_dTw": dJ_dTw, "dJ_dSte": dJ_dSte}
+            "full_tape": full,
+            "J": J, "dJ_dTw": float(dJ_dTw), "dJ_dSte": float(dJ_dSte)}
 
 
 def batch_leg(nsteps: int = 200, precision: str = "fp32", adjoint: bool = True) -> dict:
@@ -257,7 +283,8 @@ def batch_adjoint_leg(cases, solvers, tiles, nsteps: int, window: int) -> dict:
 
     import synth
     from paper_2603_22902_amd.adjoint import forward_with_checkpoints, reverse_sweep
-    from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
+    from paper_2603_22902_amd.batch import (Batch, batch_forward_to_tape, batch_forward_with_checkpoints,
+                                            batch_reverse_from_tape, batch_reverse_sweep)
 
     adj_cases = [synth.near_melting(c) for c in cases]
     for s, c in zip(solvers, adj_cases):
@@ -277,6 +304,37 @@ def batch_adjoint_leg(cases, solvers, tiles, nsteps: int, window: int) -> dict:
     t2 = time.perf_counter()
     b.close()
     del ck
+    # the same sweep from a full packed tape (no recomputation), if it fits
+    full = None
+    torch.cuda.empty_cache()
+    for s, c in zip(solvers, adj_cases):
+        s.init_case(c)
+    b = Batch(solvers)
+    b.set_tiles(tiles)
+    need = (nsteps + 1) * b.state_bytes()
+    free, _ = torch.cuda.mem_get_info()
+    if need < 0.75 * free:
+        try:
+            torch.cuda.synchronize()
+            t5 = time.perf_counter()
+            tape = batch_forward_to_tape(b, nsteps)
+            b.synchronize()
+            t6 = time.perf_counter()
+            t7 = {}
+            J2, g2 = batch_reverse_from_tape(b, tape, nsteps, timing=t7)
+            torch.cuda.synchronize()
+            t8 = time.perf_counter()
+            full = {"tape_GB": round(need / 1e9, 1), "forward_to_tape_s": round(t6 - t5, 4),
+                    "reverse_s": round(t8 - t6, 4), "reverse_steps_ms": round(t7["reverse_ms"], 2),
+                    "ratio_vs_graph_forward": round((t8 - t6) / (t1 - t0), 3),
+                    "gradients_bitwise_equal_checkpointed": bool(np.array_equal(J2, J) and np.array_equal(g2, g))}
+            del tape
+        except torch.cuda.OutOfMemoryError:
+            full = {"skipped": f"out of device memory for a {need / 1e9:.0f} GB tape"}
+    else:
+        full = {"skipped": f"a {need / 1e9:.0f} GB tape needs more than 3/4 of the free device memory"}
+    b.close()
+    torch.cuda.empty_cache()
     # the same sweeps, one case at a time
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -296,6 +354,7 @@ def batch_adjoint_leg(cases, solvers, tiles, nsteps: int, window: int) -> dict:
             "looped_single_s": round(loop, 4),
             "speedup_vs_looped": round(loop / (fwd + rev), 3),
             "gradients_bitwise_equal_looped": bool(all(np.array_equal(g[k], gl[k]) for k in range(len(gl)))),
+            "full_tape": full,
             "J_range": [float(J.min()), float(J.max())]}
 
 

@@ -7,7 +7,10 @@ wall temperatures, the latent heats and the wetting cosines, by the
 hand-written discrete adjoint of every step (2D, float32 or float64).  Long runs use checkpoint-and-
 recompute: the forward run keeps the device state every ``window`` steps;
 the reverse sweep re-runs each window forward from its checkpoint, keeping
-its states on the device, and then steps the adjoint back through it.
+its states on the device, and then steps the adjoint back through it.  When
+the whole trajectory fits in device memory (``window = 0``), the forward run
+writes every state straight into an HBM-resident tape instead and the
+reverse sweep recomputes nothing.
 
 :class:`FrozenFraction` exposes this as a ``torch.autograd.Function`` of
 (T_w, latent[N], cos_theta[N, N]), for either objective; derived parameters such as the Stefan
@@ -161,6 +164,47 @@ def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = N
     return J, g
 
 
+def tape_bytes(solver: Solver, nsteps: int) -> int:
+    """Device bytes of the full tape of an nsteps run (nsteps + 1 states)."""
+    return (nsteps + 1) * solver.state_device_bytes()
+
+
+def forward_to_tape(solver: Solver, case: dict, nsteps: int):
+    """Equilibrium start from case, then nsteps steps written straight into
+    a device tape (row j = x^j, nsteps + 1 rows, no copies); the solver's
+    own state ends at x^nsteps."""
+    solver.init_case(case)
+    tape = _states(solver, nsteps + 1)
+    solver.lbf_state_to_device(tape[0])
+    for j in range(1, nsteps + 1):
+        solver.lbf_step_states(tape[j - 1], tape[j])
+    solver.lbf_state_from_device(tape[nsteps], nsteps)
+    return tape
+
+
+def reverse_from_tape(solver: Solver, tape, nsteps: int, timing: dict = None,
+                      objective: str = "frozen_fraction") -> tuple:
+    """J and its gradient from the full tape of :func:`forward_to_tape`, with
+    no recomputation; timing (a dict) receives the milliseconds of the
+    reverse steps (events on the solver's stream)."""
+    import torch
+
+    adj = Adjoint(solver)
+    J = adj.seed(objective)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(solver.stream)
+    for j in range(nsteps - 1, -1, -1):
+        adj.step(tape[j], tape[j + 1])
+    e1.record(solver.stream)
+    adj.finish(tape[0])
+    g = adj.gradient()
+    adj.close()
+    if timing is not None:
+        torch.cuda.synchronize(solver.device)
+        timing["reverse_ms"] = e0.elapsed_time(e1)
+    return J, g
+
+
 def case_with(case: dict, T_w=None, latent=None, cos_theta=None) -> dict:
     """A copy of case whose parameters take T_face[0] = T_w, latent[:N] and
     cos_theta[:N, :N] (plain floats / arrays)."""
@@ -188,10 +232,15 @@ def case_with(case: dict, T_w=None, latent=None, cos_theta=None) -> dict:
 def frozen_fraction_and_gradient(case: dict, nsteps: int, window: int = 50, device: int = 0,
                                  objective: str = "frozen_fraction"):
     """Forward run with checkpoints, then the reverse sweep: (J, gradient)
-    of the objective ("frozen_fraction" or "front")."""
+    of the objective ("frozen_fraction" or "front").  window = 0 keeps the
+    whole trajectory on the device (no recomputation)."""
     s = Solver(case["params"], device=device)
-    ck = forward_with_checkpoints(s, case, nsteps, window)
-    J, g = reverse_sweep(s, ck, nsteps, window, objective=objective)
+    if window == 0:
+        tape = forward_to_tape(s, case, nsteps)
+        J, g = reverse_from_tape(s, tape, nsteps, objective=objective)
+    else:
+        ck = forward_with_checkpoints(s, case, nsteps, window)
+        J, g = reverse_sweep(s, ck, nsteps, window, objective=objective)
     s.close()
     return J, g
 
@@ -210,7 +259,7 @@ def _torch_function():
             c = case_with(case, float(T_w), latent.detach().cpu().numpy(),
                           cos_theta.detach().cpu().numpy())
             s = Solver(c["params"], device=device)
-            ck = forward_with_checkpoints(s, c, nsteps, window)
+            ck = forward_to_tape(s, c, nsteps) if window == 0 else forward_with_checkpoints(s, c, nsteps, window)
             d = s.lbf_diagnostics()
             N = s.N
             frz = [p for p in range(N) if c["params"]["freezes"][p]]
@@ -224,7 +273,10 @@ def _torch_function():
 
         @staticmethod
         def backward(ctx, gJ):
-            _, g = reverse_sweep(ctx.solver, ctx.ck, ctx.nsteps, ctx.window, objective=ctx.objective)
+            if ctx.window == 0:
+                _, g = reverse_from_tape(ctx.solver, ctx.ck, ctx.nsteps, objective=ctx.objective)
+            else:
+                _, g = reverse_sweep(ctx.solver, ctx.ck, ctx.nsteps, ctx.window, objective=ctx.objective)
             N = ctx.solver.N
             gT = torch.tensor(g["T_face"][0], dtype=torch.float64) * gJ
             gL = torch.tensor(g["latent"][:N], dtype=torch.float64) * gJ

@@ -225,3 +225,37 @@ def batch_reverse_sweep(batch: Batch, ck, nsteps: int, window: int, objective: s
         timing["recompute_ms"] = sum(ev[i].elapsed_time(ev[i + 1]) for i in range(0, len(ev), 3))
         timing["reverse_ms"] = sum(ev[i + 1].elapsed_time(ev[i + 2]) for i in range(0, len(ev), 3))
     return J, g
+
+
+def batch_forward_to_tape(batch: Batch, nsteps: int):
+    """nsteps batched steps from the members' current states, every packed
+    state written straight into a device tape (row j = x^j, nsteps + 1
+    rows); the members' own states are not advanced."""
+    tape = batch.states(nsteps + 1)
+    batch.state_to_device(tape[0])
+    for j in range(1, nsteps + 1):
+        batch.step_states(tape[j - 1], tape[j])
+    return tape
+
+
+def batch_reverse_from_tape(batch: Batch, tape, nsteps: int, objective: str = "frozen_fraction",
+                            timing: dict = None) -> tuple:
+    """(J[ncase], grad[ncase, 22]) from the full tape of
+    :func:`batch_forward_to_tape`, with no recomputation; timing (a dict)
+    receives the milliseconds of the reverse steps."""
+    import torch
+
+    adj = BatchAdjoint(batch)
+    J = adj.seed(tape[nsteps], objective)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(batch.stream)
+    for j in range(nsteps - 1, -1, -1):
+        adj.step(tape[j], tape[j + 1])
+    e1.record(batch.stream)
+    adj.finish(tape[0])
+    g = adj.gradient()
+    adj.close()
+    if timing is not None:
+        batch.synchronize()
+        timing["reverse_ms"] = e0.elapsed_time(e1)
+    return J, g

@@ -73,6 +73,16 @@ def test_checkpoint_window_does_not_change_the_gradient():
         assert J == ref[0] and np.array_equal(g["raw"], ref[1]), window
 
 
+@pytest.mark.parametrize("objective", ["frozen_fraction", "front"])
+def test_full_tape_equals_checkpointed_gradient(objective):
+    """window = 0 writes every state of the forward run into a device tape
+    and recomputes nothing: the same states, so the same gradient bitwise."""
+    case = make_case(*CASES[1], precision="fp32")
+    J0, g0 = _grad(case, 25, 7, objective=objective)
+    J1, g1 = _grad(case, 25, 0, objective=objective)
+    assert J0 == J1 and np.array_equal(g0["raw"], g1["raw"])
+
+
 def test_float32_adjoint_close_to_float64():
     """float32 storage and arithmetic: the gradient of the same case within
     1e-3 relative of the float64 one (measured ~1e-5)."""

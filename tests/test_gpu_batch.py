@@ -154,6 +154,23 @@ def test_batched_adjoint_equals_single_case_sweeps(precision, objective):
         assert np.array_equal(g[k], gk["raw"]), (k, g[k], gk["raw"])
 
 
+def test_batched_full_tape_equals_checkpointed():
+    """The batched forward written into a full packed tape (no
+    recomputation) gives the checkpointed batched gradient bitwise."""
+    from paper_2603_22902_amd.batch import (Batch, batch_forward_to_tape, batch_forward_with_checkpoints,
+                                            batch_reverse_from_tape, batch_reverse_sweep)
+    cases = _adj_cases("fp32")
+    n = 12
+    b = Batch(_solvers(cases))
+    tape = batch_forward_to_tape(b, n)
+    J1, g1 = batch_reverse_from_tape(b, tape, n)
+    b.close()
+    b = Batch(_solvers(cases))
+    ck = batch_forward_with_checkpoints(b, n, 5)
+    J0, g0 = batch_reverse_sweep(b, ck, n, 5)
+    assert np.array_equal(J0, J1) and np.array_equal(g0, g1)
+
+
 def test_batched_adjoint_through_graph_replays():
     """The forward pass replayed from the captured graph gives the same
     batched gradient as eager steps."""
