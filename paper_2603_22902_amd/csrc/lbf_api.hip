@@ -1163,9 +1163,13 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
       bc.first_tblock = G.tblocks;
       G.tblocks += bc.nblocks;
     }
-    HIPCHK(c0, hipMemcpyAsync(ba->base + G.off, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
-           "hipMemcpyAsync");
-    HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    hipError_t e = hipMemcpyAsync(ba->base + G.off, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+      batch_adj_free(ba);
+      return hip_fail(c0, e, "batched adjoint case table");
+    }
   }
   *out = ba;
   return LBF_OK;
