@@ -70,6 +70,11 @@ def measured_traffic(workload: str, precision: str):
     return rec.get("bytes_per_launch")
 
 
+def traffic_rate(workload: str, precision: str, ms: float) -> float:
+    """Measured HBM bytes per second of the collide kernel at ms per launch."""
+    return measured_traffic(workload, precision) / (ms * 1e-3)
+
+
 def make_case(workload: str, precision: str):
     import synth
     fn = synth.WORKLOADS[workload]
@@ -421,6 +426,12 @@ def main():
     print(f"[bench] moments {ms_mom * 1e3:.1f} us, collide {ms_col * 1e3:.1f} us per launch; "
           f"front {diag['front']:.4f} nonfinite {diag['nonfinite']}", file=sys.stderr, flush=True)
 
+    # same-box HBM rates of a plain float4 copy and read sweep, for context
+    from paper_2603_22902_amd.lbfreeze import bandwidth_probe
+    bw = bandwidth_probe(s.device)
+    probe = {"copy_GB_s": round(bw["copy"] / 1e9, 1), "read_GB_s": round(bw["read"] / 1e9, 1),
+             "collide_raw_vs_copy": round(traffic_rate(args.workload, args.precision, ms_col) / bw["copy"], 3)
+             if measured_traffic(args.workload, args.precision) else None}
     elt = 8 if args.precision == "fp64" else 4
     bpc = algorithmic_bytes_per_cell(prm["dim"], prm["nphase"], elt)
     achieved = bpc["collide"] * ncell / (ms_col * 1e-3) / 1e9
@@ -442,6 +453,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "collide_kernel", "kernel_us": round(ms_col * 1e3, 2),
                      "bytes_per_cell": bpc["collide"]},
+        "bandwidth_probe": probe,
         "diagnostics": dlog,
         "kernels": {
             "moment_kernel": {"us": round(ms_mom * 1e3, 2), "bytes_per_cell": bpc["moments"],

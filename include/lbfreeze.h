@@ -324,6 +324,16 @@ lbf_status lbf_destroy(lbf_ctx* ctx);
 const char* lbf_last_error(const lbf_ctx* ctx);
 const char* lbf_status_string(lbf_status s);
 
+/* HBM bandwidth probe, context for the kernels' roofline: the best rate of a
+ * float4 grid-stride copy a -> b and of a float4 read-only sweep of a, over
+ * a few launch shapes, each timed over reps launches with HIP events on
+ * hip_stream (synchronises it).  a and b: caller-owned device buffers of
+ * `bytes` each (16-byte aligned, distinct; the last 16 bytes of b are
+ * scratch).  Rates in bytes per second (copy counts read + write).
+ * LBF_EINVAL for bad arguments, LBF_EDEVICE on a HIP error. */
+lbf_status lbf_bandwidth_probe(void* a, void* b, size_t bytes, void* hip_stream, int reps, double* copy_bytes_per_s,
+                               double* read_bytes_per_s);
+
 #ifdef __cplusplus
 }
 #endif

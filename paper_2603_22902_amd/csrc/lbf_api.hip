@@ -1272,6 +1272,82 @@ lbf_status lbf_destroy(lbf_ctx* c) {
 
 const char* lbf_last_error(const lbf_ctx* c) { return c ? c->err.c_str() : ""; }
 
+}  // extern "C"
+
+// ----- bandwidth probe (context for the roofline) -------------------------
+namespace {
+
+__global__ void __launch_bounds__(512) probe_copy4(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                   long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(512) probe_read4(const float4* __restrict__ src, float* __restrict__ sink,
+                                                   long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  float acc = 0.f;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float4 v = src[i];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  // a store only for an impossible sum keeps the loads without writing
+  if (acc == -1.5f) sink[0] = acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbf_status lbf_bandwidth_probe(void* a, void* b, size_t bytes, void* hip_stream, int reps, double* copy_bytes_per_s,
+                               double* read_bytes_per_s) {
+  if (!a || !b || a == b || bytes < 4096 || reps < 1 || !copy_bytes_per_s || !read_bytes_per_s) return LBF_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) return LBF_EINVAL;
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const long long n = (long long)((bytes - 16) / 16);  // the last 16 bytes of b are the read sink
+  const float4* src = static_cast<const float4*>(a);
+  float4* dst = static_cast<float4*>(b);
+  float* sink = reinterpret_cast<float*>(static_cast<char*>(b) + (size_t)n * 16);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return LBF_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return LBF_EDEVICE;
+  }
+  const int grids[4] = {1024, 4096, 16384, 65536};
+  const int blocks[2] = {256, 512};
+  double best_copy = 0.0, best_read = 0.0;
+  hipError_t e = hipSuccess;
+  for (int gi = 0; gi < 4 && e == hipSuccess; ++gi)
+    for (int bi = 0; bi < 2 && e == hipSuccess; ++bi)
+      for (int kind = 0; kind < 2 && e == hipSuccess; ++kind) {
+        const dim3 grid(grids[gi]), block(blocks[bi]);
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+          if (r == 1) e = hipEventRecord(e0, s);
+          if (kind == 0)
+            hipLaunchKernelGGL(probe_copy4, grid, block, 0, s, src, dst, n);
+          else
+            hipLaunchKernelGGL(probe_read4, grid, block, 0, s, src, sink, n);
+          if (e == hipSuccess) e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms > 0.f) {
+          const double rate = (kind == 0 ? 2.0 : 1.0) * 16.0 * (double)n * reps / (ms * 1e-3);
+          if (kind == 0 && rate > best_copy) best_copy = rate;
+          if (kind == 1 && rate > best_read) best_read = rate;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return LBF_EDEVICE;
+  *copy_bytes_per_s = best_copy;
+  *read_bytes_per_s = best_read;
+  return LBF_OK;
+}
+
 const char* lbf_status_string(lbf_status s) {
   switch (s) {
     case LBF_OK: return "ok";

@@ -1,6 +1,7 @@
 // HIP kernels of the coupled LB solver and their launchers.
 //
-//   moment_kernel   phi_p^n, f_s^n of every cell (first pass of a step)
+//   moment_kernel   phi_p^n, f_s^n of every cell (first pass of a step;
+//                   moment_kernel_v4: four cells per thread, float32 storage)
 //   collide_kernel  finite differences, sources, collisions and push
 //                   streaming (or, with MOMENTS, one macroscopic field at
 //                   the current time level)
@@ -56,6 +57,67 @@ __global__ void __launch_bounds__(MOMENT_THREADS)
   a.aout = aout;
   const int cell = blockIdx.x * MOMENT_THREADS + threadIdx.x;
   if (cell < P.ncell) moment_cell<C>(a, P, cell);
+}
+
+// Moments pass over four consecutive cells per thread with 16-byte loads and
+// stores (float32 storage, cell count a multiple of 4): the wider loads
+// stream closer to the HBM read rate than one 4-byte load per plane and cell.
+// Each cell's arithmetic is that of moment_cell, in the same order, so the
+// result is bitwise the same.
+template <class C>
+__global__ void __launch_bounds__(MOMENT_THREADS)
+    moment_kernel_v4(const float* __restrict__ pin, const float* __restrict__ ain, float* __restrict__ aout,
+                     const KParams* __restrict__ kp) {
+  using R = typename C::R;
+  constexpr int Q = C::Q, NP = C::NP;
+  const KParams& P = *kp;
+  const long long nc = P.ncell;
+  const long long c0 = 4LL * ((long long)blockIdx.x * MOMENT_THREADS + threadIdx.x);
+  if (c0 >= nc) return;
+  const float4 dv = *reinterpret_cast<const float4*>(plane(ain, C::A_DIV, nc) + c0);
+  const float4 qv = *reinterpret_cast<const float4*>(plane(ain, C::A_Q, nc) + c0);
+  const float dva[4] = {dv.x, dv.y, dv.z, dv.w};
+  const float qva[4] = {qv.x, qv.y, qv.z, qv.w};
+  R idiv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) idiv[k] = R(1) / (R(1) - R(0.5) * R(dva[k]));
+  R phi[4][NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    R sum[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float4 v = *reinterpret_cast<const float4*>(plane(pin, (1 + p) * Q + i, nc) + c0);
+      sum[0] += R(v.x);
+      sum[1] += R(v.y);
+      sum[2] += R(v.z);
+      sum[3] += R(v.w);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) phi[k][p] = sum[k] * idiv[k];
+  }
+  double sh[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float4 v = *reinterpret_cast<const float4*>(plane(pin, (NP + 1) * Q + i, nc) + c0);
+    sh[0] += double(v.x);
+    sh[1] += double(v.y);
+    sh[2] += double(v.z);
+    sh[3] += double(v.w);
+  }
+  float fsv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double rhoH = sh[k] + 0.5 * double(R(qva[k]));
+    double T, fl;
+    invert<NP>(P, phi[k], rhoH, T, fl);
+    fsv[k] = float(R(1.0 - fl));
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    *reinterpret_cast<float4*>(plane(aout, p, nc) + c0) =
+        make_float4(float(phi[0][p]), float(phi[1][p]), float(phi[2][p]), float(phi[3][p]));
+  *reinterpret_cast<float4*>(plane(aout, C::A_FS, nc) + c0) = make_float4(fsv[0], fsv[1], fsv[2], fsv[3]);
 }
 
 // The buffers are separate kernel parameters so that the compiler knows
@@ -332,9 +394,23 @@ inline hipError_t launch_step(StepArgs<S> a, const KParams& hostP, const KParams
   a.nblocks = g.nblocks;
   a.mom = a.aout;
   const int mb = (int)((hostP.ncell + MOMENT_THREADS - 1) / MOMENT_THREADS);
-  if (passes & 1)
-    hipLaunchKernelGGL((moment_kernel<C>), dim3(mb), dim3(MOMENT_THREADS), 0, s, a.pin, a.ain, a.aout,
-                       a, dP);
+  if (passes & 1) {
+    // float4 path: float32 storage, whole quads of cells, 16-byte aligned
+    // planes (caller-supplied device states need not be)
+    bool v4 = false;
+    if constexpr (sizeof(S) == 4)
+      v4 = hostP.ncell % 4 == 0 && ((reinterpret_cast<uintptr_t>(a.pin) | reinterpret_cast<uintptr_t>(a.ain) |
+                                     reinterpret_cast<uintptr_t>(a.aout)) & 15) == 0;
+    if (v4) {
+      const int mb4 = (int)((hostP.ncell / 4 + MOMENT_THREADS - 1) / MOMENT_THREADS);
+      hipLaunchKernelGGL((moment_kernel_v4<C>), dim3(mb4), dim3(MOMENT_THREADS), 0, s,
+                         reinterpret_cast<const float*>(a.pin), reinterpret_cast<const float*>(a.ain),
+                         reinterpret_cast<float*>(a.aout), dP);
+    } else {
+      hipLaunchKernelGGL((moment_kernel<C>), dim3(mb), dim3(MOMENT_THREADS), 0, s, a.pin, a.ain, a.aout,
+                         a, dP);
+    }
+  }
   if (!(passes & 2)) return hipGetLastError();
   if (moments)
     hipLaunchKernelGGL((collide_kernel<C, true>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin,

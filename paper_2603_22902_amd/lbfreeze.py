@@ -96,6 +96,7 @@ def lib():
         L.lbf_batch_adjoint_finish.argtypes = [vp, vp]
         L.lbf_batch_adjoint_gradient.argtypes = [vp, _PD]
         L.lbf_batch_adjoint_destroy.argtypes = [vp]
+        L.lbf_bandwidth_probe.argtypes = [vp, vp, ctypes.c_size_t, vp, ctypes.c_int, _PD, _PD]
         L.lbf_get_moments.argtypes = [vp, ctypes.c_uint, _PD]
         L.lbf_get_populations.argtypes = [vp, _PD]
         L.lbf_get_aux.argtypes = [vp, _PD]
@@ -121,7 +122,7 @@ def lib():
                      "lbf_batch_state_bytes", "lbf_batch_state_to_device", "lbf_batch_step_states",
                      "lbf_batch_adjoint_bytes", "lbf_batch_adjoint_create", "lbf_batch_adjoint_seed",
                      "lbf_batch_adjoint_step", "lbf_batch_adjoint_finish", "lbf_batch_adjoint_gradient",
-                     "lbf_batch_adjoint_destroy"):
+                     "lbf_batch_adjoint_destroy", "lbf_bandwidth_probe"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -336,3 +337,22 @@ class Solver:
     # -- convenience ------------------------------------------------------
     def init_case(self, case: dict):
         self.lbf_init_fields(case["phi"], case["T"], case.get("u"), case.get("p"))
+
+
+def bandwidth_probe(device: int = 0, mib: int = 2048, reps: int = 5) -> dict:
+    """HBM rates of a float4 copy and a float4 read sweep on the device
+    (lbf_bandwidth_probe), over two buffers of mib MiB: bytes per second."""
+    import torch
+
+    n = mib << 20
+    a = torch.zeros(n, dtype=torch.uint8, device=device)
+    b = torch.empty(n, dtype=torch.uint8, device=device)
+    stream = torch.cuda.current_stream(device)
+    torch.cuda.synchronize(device)
+    c = np.zeros(1)
+    r = np.zeros(1)
+    s = lib().lbf_bandwidth_probe(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), n,
+                                  ctypes.c_void_p(stream.cuda_stream), int(reps), _ptr(c), _ptr(r))
+    if s != LBF_OK:
+        raise LbfError(s, "lbf_bandwidth_probe")
+    return {"copy": float(c[0]), "read": float(r[0])}

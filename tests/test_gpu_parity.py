@@ -205,3 +205,23 @@ def test_nan_is_reported_and_sticky():
     with pytest.raises(LbfError) as e:
         s.lbf_diagnostics()
     assert e.value.status == LBF_ENAN
+
+
+def test_bandwidth_probe_rates_are_plausible():
+    """lbf_bandwidth_probe: a float4 copy and read sweep give rates between
+    0.5 and 10 TB/s, and misaligned or aliased buffers are refused."""
+    import ctypes
+
+    import torch
+
+    from paper_2603_22902_amd import lbfreeze
+    bw = lbfreeze.bandwidth_probe(0, mib=256, reps=2)
+    print("bandwidth probe", bw)
+    assert 0.5e12 < bw["copy"] < 10e12 and 0.5e12 < bw["read"] < 10e12
+    a = torch.zeros(1 << 20, dtype=torch.uint8, device=0)
+    c, r = np.zeros(1), np.zeros(1)
+    L = lbfreeze.lib()
+    p = ctypes.c_void_p(a.data_ptr())
+    assert L.lbf_bandwidth_probe(p, p, 1 << 19, None, 1, lbfreeze._ptr(c), lbfreeze._ptr(r)) == lbfreeze.LBF_EINVAL
+    assert L.lbf_bandwidth_probe(ctypes.c_void_p(a.data_ptr() + 4), ctypes.c_void_p(a.data_ptr() + (1 << 19)),
+                                 1 << 18, None, 1, lbfreeze._ptr(c), lbfreeze._ptr(r)) == lbfreeze.LBF_EINVAL
