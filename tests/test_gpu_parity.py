@@ -225,3 +225,33 @@ def test_bandwidth_probe_rates_are_plausible():
     assert L.lbf_bandwidth_probe(p, p, 1 << 19, None, 1, lbfreeze._ptr(c), lbfreeze._ptr(r)) == lbfreeze.LBF_EINVAL
     assert L.lbf_bandwidth_probe(ctypes.c_void_p(a.data_ptr() + 4), ctypes.c_void_p(a.data_ptr() + (1 << 19)),
                                  1 << 18, None, 1, lbfreeze._ptr(c), lbfreeze._ptr(r)) == lbfreeze.LBF_EINVAL
+
+
+@pytest.mark.parametrize("dim,shape,N", [(3, (24, 20, 16), 4), (2, (96, 40), 3)])
+def test_moments_float4_path_bitwise_equals_per_cell_path(dim, shape, N):
+    """The four-cells-per-thread moments pass (16-byte aligned float32
+    planes) and the one-cell-per-thread pass (taken for planes that are not
+    16-byte aligned) give bitwise the same step."""
+    import torch
+
+    from paper_2603_22902_amd import Solver
+    case = synth.stress(synth.small(dim=dim, shape=shape, nphase=N, precision="fp32"), phi_noise=1e-4)
+    s = Solver(case["params"])
+    s.init_case(case)
+    s.lbf_step(3)
+    nb = s.state_device_bytes()
+    assert s.ncell % 4 == 0
+    buf = torch.empty(4 * nb + 1024, dtype=torch.uint8, device=s.device)
+    base = (256 - buf.data_ptr() % 256) % 256
+    al = [buf[base + k * nb: base + (k + 1) * nb] for k in range(2)]       # 16-byte aligned
+    mis = [buf[base + 2 * nb + 4 + k * nb: base + 2 * nb + 4 + (k + 1) * nb] for k in range(2)]  # 4 off
+    assert al[0].data_ptr() % 16 == 0 and mis[0].data_ptr() % 16 == 4
+    s.lbf_state_to_device(al[0])
+    s.lbf_state_to_device(mis[0])
+    for _ in range(2):
+        s.lbf_step_states(al[0], al[1])
+        s.lbf_step_states(mis[0], mis[1])
+        al.reverse()
+        mis.reverse()
+    torch.cuda.synchronize()
+    assert torch.equal(al[0], mis[0])
