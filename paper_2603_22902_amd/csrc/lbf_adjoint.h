@@ -253,9 +253,21 @@ __host__ __device__ inline void nb_fields(const AdjArgs<C>& a, const KParams& P,
 // Pass 2: reverse of the collide pass for one cell.  gpar accumulates the
 // cell's parameter-gradient contributions (NPAR doubles).
 // ---------------------------------------------------------------------------
+// The neighbour fields of the forward recompute read from global memory
+// (nb_fields); a tiled kernel reads them from its LDS ring instead.
 template <class C>
-__host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KParams& P, int cell,
-                                                 double* gpar) {
+struct NbGlobal {
+  const AdjArgs<C>* a;
+  int gx, gy, w;
+  __host__ __device__ void operator()(const KParams& P, int i, typename C::R* phi, typename C::R& fs,
+                                      typename C::R& rho, typename C::R* up) const {
+    nb_fields<C>(*a, P, gx, gy, w, i, phi, fs, rho, up);
+  }
+};
+
+template <class C, class NB>
+__host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KParams& P, int cell, double* gpar,
+                                                 const NB& nb) {
   using R = typename C::R;
   using ST = typename C::S;
   using Lt = typename C::L;
@@ -287,7 +299,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   for (int d = 0; d < DIM; ++d) grho[d] = gu[d] = R(0);
   for (int i = 1; i < Q; ++i) {
     R X[NP], fsn, rn, un[DIM];
-    nb_fields<C>(a, P, gx, gy, w, i, X, fsn, rn, un);
+    nb(P, i, X, fsn, rn, un);
     const R wi = wgt<R, DIM>(i);
     for (int p = 0; p < NP; ++p) {
       const R t = wi * X[p];
@@ -833,6 +845,18 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   wplane(a, L::L_FS, nc)[cell] = fspb;
   wplane(a, L::L_Q, nc)[cell] = qpb;
   wplane(a, L::M_RHOH, nc)[cell] = R(rhoH);  // for pass 3 of this cell
+}
+
+template <class C>
+__host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KParams& P, int cell, double* gpar) {
+  const int area = (int)P.area;
+  const int w = cell / area, lat = cell - w * area;
+  NbGlobal<C> nb;
+  nb.a = &a;
+  nb.gx = lat % P.nx;
+  nb.gy = lat / P.nx;
+  nb.w = w;
+  adj_collide_cell<C>(a, P, cell, gpar, nb);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,7 +1,8 @@
 // HIP kernels of the reverse (adjoint) step and their launchers.
 //
 //   adj_moment_kernel        pass 1: forward moments of x^n
-//   adj_collide_kernel       pass 2: reverse of the collide pass
+//   adj_collide_tile_kernel  pass 2: reverse of the collide pass (row tiles
+//                            marching the wall-normal axis, LDS ring)
 //   adj_gather_kernel        pass 3: transpose of the finite differences and
 //                            of the moments (SEED: start from the objective)
 //   adj_objective_kernel     sums A = sum f_s psi, B = sum psi of a state
@@ -62,20 +63,6 @@ __global__ void __launch_bounds__(ADJ_THREADS)
   const KParams& P = *kp;
   const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
   if (cell < P.ncell) adj_moment_cell<C>(a, P, cell);
-}
-
-// The collide reverse holds the forward recompute and the whole reverse of a
-// cell; capped at 256 registers (two waves per SIMD), the gather at 128.
-template <class C>
-__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
-    adj_collide_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
-  const KParams& P = *kp;
-  double g[NPAR];
-#pragma unroll
-  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
-  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
-  if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
-  block_sum<NPAR, true>(g, part);
 }
 
 template <class C, bool SEED>
@@ -155,9 +142,6 @@ __device__ inline void gather_tile_block(const AdjArgs<C>& a, const KParams& P, 
   block_sum_to<NPAR, true, C::NT>(g, row);
 }
 
-// The row of a block is its tile index (the block number after the XCD
-// remap), so that a batched launch, whose remap spans many cases, fills
-// the same rows in the same order.
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
     adj_gather_tile_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part, int ntx,
@@ -171,6 +155,103 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
   sa.nblocks = nblocks;
   const int t = xcd_remap(blockIdx.x, nblocks);
   gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, part + (long long)t * NPAR);
+}
+
+// The collide reverse with its neighbour fields (phi_p, f_s, rho, u^{n-1}
+// of the footprint, wall ghosts included) staged in the forward kernel's LDS
+// ring: the block marches its tile along the wall-normal axis and fills the
+// ring with the forward fill, from the moments of x^n (x^{n+1}'s lagged
+// planes, or the recomputed work planes, laid out alike).  It holds the
+// forward recompute and the whole reverse of a cell: capped at 256 registers
+// (two waves per SIMD); the gather at 128.
+template <class C>
+struct NbLds {
+  const Smem<C>* sm;
+  int fc, w;
+  __host__ __device__ void operator()(const KParams&, int i, typename C::R* phi, typename C::R& fs,
+                                      typename C::R& rho, typename C::R* up) const {
+    using Lt = typename C::L;
+    const int s = slot(w + Lt::cw(i));
+    const int f = fc + Lt::cl0(i) + (C::DIM == 3 ? Lt::cl1(i) * C::LX : 0);
+#pragma unroll
+    for (int p = 0; p < C::NP; ++p) phi[p] = sm->phi[s][p][f];
+    fs = sm->fs[s][f];
+    rho = sm->rho[s][f];
+#pragma unroll
+    for (int d = 0; d < C::DIM; ++d) up[d] = sm->u[s][d][f];
+  }
+};
+
+// Fill arguments of the forward fill for the reverse step's x^n.
+template <class C>
+__host__ __device__ inline StepArgs<typename C::S> fill_args(const AdjArgs<C>& a, int ntx, int nty, int chunk,
+                                                             int nblocks) {
+  using S = typename C::S;
+  // the recomputed moments (work planes M_PHI.., M_FS) stand in for the
+  // moment planes phi_p.., f_s when x^{n+1} is not given: same order, type
+  static_assert(sizeof(typename C::R) == sizeof(S), "work planes and state share the element type");
+  static_assert(AdjLayout<C>::M_PHI == 0 && AdjLayout<C>::M_FS == C::A_FS, "moment plane order");
+  StepArgs<S> sa;
+  sa.pin = a.pin;
+  sa.ain = a.ain;
+  sa.mom = a.mom ? a.mom : reinterpret_cast<const S*>(a.work);
+  sa.ntx = ntx;
+  sa.nty = nty;
+  sa.chunk = chunk;
+  sa.nblocks = nblocks;
+  return sa;
+}
+
+// One block of the tiled collide reverse: tile and chunk bp, parameter terms
+// added to row (NPAR values).
+template <class C>
+__device__ inline void collide_tile_block(const AdjArgs<C>& a, const StepArgs<typename C::S>& sa, const KParams& P,
+                                          const BlockPos& bp, Smem<C>& sm, double* row) {
+  const int tid = threadIdx.x;
+  const int tx = tid % C::TX, ty = tid / C::TX;
+  const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
+  const bool own = gx < P.nx && (C::DIM == 2 || gy < P.ny);
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  if (bp.w0 == 0) {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(sa, P, sm, bp, f, 0);
+    __syncthreads();
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(sa, P, sm, bp, f, -1);
+  } else {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(sa, P, sm, bp, f, bp.w0 - 1);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(sa, P, sm, bp, f, bp.w0);
+  }
+  __syncthreads();
+  for (int w = bp.w0; w < bp.w1; ++w) {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(sa, P, sm, bp, f, w + 1);
+    __syncthreads();
+    if (own) {
+      NbLds<C> nb;
+      nb.sm = &sm;
+      nb.fc = (C::DIM == 3) ? (ty + 1) * C::LX + tx + 1 : tx + 1;
+      nb.w = w;
+      const int cell = w * (int)P.area + ((C::DIM == 3) ? gy * P.nx + gx : gx);
+      adj_collide_cell<C>(a, P, cell, g, nb);
+    }
+    __syncthreads();
+  }
+  block_sum_to<NPAR, true, C::NT>(g, row);
+}
+
+// The row of a block is its tile index (the block number after the XCD
+// remap), in both tiled passes, so that a batched launch, whose remap spans
+// many cases, fills the same rows in the same order.
+
+template <class C>
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
+    adj_collide_tile_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part, int ntx,
+                            int nty, int chunk, int nblocks) {
+  const KParams& P = *kp;
+  __shared__ Smem<C> sm;
+  const StepArgs<typename C::S> sa = fill_args<C>(a, ntx, nty, chunk, nblocks);
+  const int t = xcd_remap(blockIdx.x, nblocks);
+  collide_tile_block<C>(a, sa, P, block_pos_local<C>(sa, P, t), sm, part + (long long)t * NPAR);
 }
 
 template <class C>
@@ -233,14 +314,18 @@ inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* 
   const dim3 grid(nb), block(ADJ_THREADS);
   switch (pass) {
     case 0: hipLaunchKernelGGL((adj_moment_kernel<C>), grid, block, 0, s, a, dP); break;
-    case 1: hipLaunchKernelGGL((adj_collide_kernel<C>), grid, block, 0, s, a, dP, part); break;
+    case 1:
     case 2: {
       // the gradient rows of the buffer layout assume 128-cell rows and
       // chunks of at least two layers in 2D
       static_assert(DIM != 2 || (C::TX == 128 && C::TY == 1), "2D adjoint tile must be a 128-cell row");
       const Geometry g = step_geometry<C>(P);
-      hipLaunchKernelGGL((adj_gather_tile_kernel<C>), dim3(g.nblocks), dim3(C::NT), 0, s, a, dP, part, g.ntx,
-                         g.nty, g.chunk, g.nblocks);
+      if (pass == 1)
+        hipLaunchKernelGGL((adj_collide_tile_kernel<C>), dim3(g.nblocks), dim3(C::NT), 0, s, a, dP, part, g.ntx,
+                           g.nty, g.chunk, g.nblocks);
+      else
+        hipLaunchKernelGGL((adj_gather_tile_kernel<C>), dim3(g.nblocks), dim3(C::NT), 0, s, a, dP, part, g.ntx,
+                           g.nty, g.chunk, g.nblocks);
       break;
     }
     case 3: hipLaunchKernelGGL((adj_gather_kernel<C, true>), grid, block, 0, s, a, dP, part); break;

@@ -1057,7 +1057,10 @@ struct lbf_batch_adj {
 
 namespace {
 
-size_t batch_adj_table_bytes(int n) { return lbf::align256((size_t)n * sizeof(lbf::BatchAdjCase)); }
+// case table, then the cases' parameter blocks
+size_t batch_adj_table_bytes(int n) {
+  return lbf::batch_adj_params_offset(n) + lbf::align256((size_t)n * sizeof(lbf::KParams));
+}
 
 // Buffer layout: per group a case table, then each case's adjoint buffer in
 // caller order.  Returns the total; fills the offsets if given.
@@ -1123,6 +1126,7 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
     G.cblocks = G.tblocks = 0;
     if (g.ctx.empty()) continue;
     std::vector<lbf::BatchAdjCase> t(g.ctx.size());
+    std::vector<lbf::KParams> kps(g.ctx.size());
     for (size_t k = 0; k < g.ctx.size(); ++k) {
       lbf_ctx* c = g.ctx[k];
       lbf_adj* a = new (std::nothrow) lbf_adj();
@@ -1139,7 +1143,7 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
       a->J = 0.0;
       ba->adj[g.user[k]] = a;
       lbf::BatchAdjCase& bc = t[k];
-      bc.P = kp_ptr(c);
+      kps[k] = c->kp;
       bc.soff = g.soff[k];
       bc.pop_bytes = (long long)c->lay.pop_bytes;
       for (int j = 0; j < 2; ++j) {
@@ -1153,6 +1157,7 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
       bc.cblocks = a->lay.cblocks;
       bc.first_cblock = G.cblocks;
       G.cblocks += bc.cblocks;
+      // the single-case tile geometry, which the gradient rows follow
       const lbf::Geometry geo = c->prm.precision == LBF_FP64
                                     ? lbf::step_geometry<lbf::CfgOf<2, 1, double, double>>(c->kp)
                                     : lbf::step_geometry<lbf::CfgOf<2, 1, float, float>>(c->kp);
@@ -1165,6 +1170,9 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
     }
     hipError_t e = hipMemcpyAsync(ba->base + G.off, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice,
                                   b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ba->base + G.off + lbf::batch_adj_params_offset(G.n), kps.data(),
+                         kps.size() * sizeof(kps[0]), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
       batch_adj_free(ba);
@@ -1209,7 +1217,7 @@ lbf_status lbf_batch_adjoint_step(lbf_batch_adj* ba, const void* state, const vo
     const lbf_batch_adj::Group& G = ba->g[gi];
     if (!G.n) continue;
     const lbf::Ops* ops = b->g[gi].ctx[0]->ops;
-    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, G.cblocks, state, next, ba->cur, b->stream),
+    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, b->stream),
            "batched collide reverse");
     HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, b->stream),
            "batched gather");

@@ -1,10 +1,12 @@
 // Batched reverse step: the two per-step passes of the reverse step (collide
 // reverse, tiled gather) for many 2D cases of one phase count, one launch
 // each.  A block finds its case in the case table (binary search over the
-// cases' first block numbers), copies the case's parameter block into LDS and
-// runs the single-case phase functions.  Each case keeps the block
-// decomposition and the gradient rows of its single-case reverse step, so its
-// gradient is bitwise the one a single-case sweep gives.
+// cases' first block numbers) and runs the single-case phase functions with
+// the case's parameter block, read through a restrict pointer into a
+// contiguous array of the group's blocks (scalar loads, as in the
+// single-case kernels).  Each case keeps the tile decomposition and the
+// gradient rows of its single-case reverse step, so its gradient is bitwise
+// the one a single-case sweep gives.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,14 +20,13 @@ namespace lbf {
 // are packed batch states (soff, pop_bytes as in BatchCase); the adjoint
 // buffers are the case's own (layout of the single-case reverse step).
 struct BatchAdjCase {
-  const KParams* P;
   long long soff, pop_bytes;
   void* lp[2];
   void* la[2];
   void* work;
   double* part;                       // gradient rows of the case
-  int cblocks, first_cblock;          // collide reverse: ceil(ncell / 256) blocks
-  int ntx, nty, chunk, nblocks;       // tiled gather geometry (single-case step geometry)
+  int cblocks, first_cblock;          // one-thread-per-cell grid (unused by the tiled passes)
+  int ntx, nty, chunk, nblocks;       // tile geometry of both passes (single-case step geometry)
   int first_tblock;
 };
 
@@ -62,31 +63,31 @@ __device__ inline AdjArgs<C> batch_adj_args(const BatchAdjCase& bc, const char* 
 }
 
 template <class C>
-__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
-    batch_adj_collide_kernel(const BatchAdjCase* __restrict__ cs, int ncase, const char* __restrict__ state,
-                             const char* __restrict__ next, int parity) {
-  __shared__ KParams P;
-  const BatchAdjCase& bc = cs[batch_adj_case(cs, ncase, blockIdx.x, true)];
-  load_params(P, bc.P);
+__global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
+    batch_adj_collide_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
+                             int nblocks, const char* __restrict__ state, const char* __restrict__ next,
+                             int parity) {
+  __shared__ Smem<C> sm;
+  const int Lg = xcd_remap(blockIdx.x, nblocks);
+  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, false));
+  const BatchAdjCase& bc = cs[k];
+  const KParams& P = kpa[k];
   const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
-  double g[NPAR];
-#pragma unroll
-  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
-  const int lb = blockIdx.x - bc.first_cblock;
-  const int cell = lb * ADJ_THREADS + threadIdx.x;
-  if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
-  block_sum_to<NPAR, true>(g, bc.part + (long long)lb * NPAR);
+  const StepArgs<typename C::S> sa = fill_args<C>(a, bc.ntx, bc.nty, bc.chunk, bc.nblocks);
+  const int t = Lg - bc.first_tblock;
+  collide_tile_block<C>(a, sa, P, block_pos_local<C>(sa, P, t), sm, bc.part + (long long)t * NPAR);
 }
 
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
-    batch_adj_gather_kernel(const BatchAdjCase* __restrict__ cs, int ncase, int nblocks,
-                            const char* __restrict__ state, const char* __restrict__ next, int parity) {
-  __shared__ KParams P;
+    batch_adj_gather_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
+                            int nblocks, const char* __restrict__ state, const char* __restrict__ next,
+                            int parity) {
   __shared__ FdaRing<C> ring;
   const int Lg = xcd_remap(blockIdx.x, nblocks);
-  const BatchAdjCase& bc = cs[batch_adj_case(cs, ncase, Lg, false)];
-  load_params(P, bc.P);
+  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, false));
+  const BatchAdjCase& bc = cs[k];
+  const KParams& P = kpa[k];
   const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
   StepArgs<typename C::S> sa;
   sa.ntx = bc.ntx;
@@ -97,21 +98,30 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
   gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, bc.part + (long long)t * NPAR);
 }
 
-// pass 0: collide reverse over cblocks blocks, 1: tiled gather over nblocks.
+// pass 0: collide reverse, 1: tiled gather, both over the cases' tiles
+// (nblocks in all).  cases: the case table followed, at the next 256-byte
+// boundary, by the cases' parameter blocks in table order, which the kernels
+// read through a restrict pointer (scalar loads, no LDS copy).
+inline size_t batch_adj_params_offset(int ncase) {
+  return ((size_t)ncase * sizeof(BatchAdjCase) + 255) & ~size_t(255);
+}
+
 template <int NP, typename S, typename R>
 inline hipError_t launch_batch_adjoint(int pass, const void* cases, int ncase, int nblocks, const void* state,
                                        const void* next, int parity, hipStream_t s) {
   using C = CfgOf<2, NP, S, R>;
   const auto* cs = static_cast<const BatchAdjCase*>(cases);
+  const auto* kpa =
+      reinterpret_cast<const KParams*>(static_cast<const char*>(cases) + batch_adj_params_offset(ncase));
   const char* st = static_cast<const char*>(state);
   const char* nx = static_cast<const char*>(next);
   if (!st || !nx || nblocks < 1) return hipErrorInvalidValue;
   if (pass == 0)
-    hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(ADJ_THREADS), 0, s, cs, ncase, st, nx,
-                       parity);
+    hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
+                       nx, parity);
   else if (pass == 1)
-    hipLaunchKernelGGL((batch_adj_gather_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, ncase, nblocks, st, nx,
-                       parity);
+    hipLaunchKernelGGL((batch_adj_gather_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
+                       nx, parity);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -110,6 +110,41 @@ void gather_tiled(const AdjArgs<C>& a, const KParams& P, double* gpar) {
   }
 }
 
+// The tiled collide reverse of adj_collide_tile_kernel, block by block, each
+// barrier phase for all threads before the next.
+template <class C>
+void collide_tiled(const AdjArgs<C>& a, const KParams& P, double* gpar) {
+  const Geometry g = step_geometry<C>(P);
+  const StepArgs<typename C::S> sa = fill_args<C>(a, g.ntx, g.nty, g.chunk, g.nblocks);
+  std::vector<Smem<C>> smv(1);
+  Smem<C>& sm = smv[0];
+  for (int b = 0; b < g.nblocks; ++b) {
+    memset(&sm, 0xff, sizeof sm);  // poison: a read of an unfilled slot shows up as NaN
+    const BlockPos bp = block_pos<C>(sa, P, b);
+    if (bp.w0 == 0) {
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(sa, P, sm, bp, f, 0);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(sa, P, sm, bp, f, -1);
+    } else {
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(sa, P, sm, bp, f, bp.w0 - 1);
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(sa, P, sm, bp, f, bp.w0);
+    }
+    for (int w = bp.w0; w < bp.w1; ++w) {
+      for (int f = 0; f < C::F; ++f) fill_layer_cell<C>(sa, P, sm, bp, f, w + 1);
+      for (int t = 0; t < C::NT; ++t) {
+        const int tx = t % C::TX, ty = t / C::TX;
+        const int gx = bp.tx0 + tx, gy = bp.ty0 + ty;
+        if (gx >= P.nx || (C::DIM == 3 && gy >= P.ny)) continue;
+        NbLds<C> nb;
+        nb.sm = &sm;
+        nb.fc = (C::DIM == 3) ? (ty + 1) * C::LX + tx + 1 : tx + 1;
+        nb.w = w;
+        const int cell = w * (int)P.area + ((C::DIM == 3) ? gy * P.nx + gx : gx);
+        adj_collide_cell<C>(a, P, cell, gpar, nb);
+      }
+    }
+  }
+}
+
 template <int DIM, int NP, typename S, typename R>
 int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, int objective, double* J,
         double* grad) {
@@ -162,7 +197,13 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, i
     a.mom = (s & 1) ? auxs[s + 1].data() : nullptr;
     if (!a.mom)
       for (int c = 0; c < (int)nc; ++c) adj_moment_cell<C>(a, P, c);
-    for (int c = 0; c < (int)nc; ++c) adj_collide_cell<C>(a, P, c, gpar.data());
+    // the tiled collide reverse of the GPU kernel on every third step (from
+    // x^{n+1}'s moments or the recomputed ones, by the parity above), the
+    // per-cell one otherwise
+    if (s % 3 == 1)
+      collide_tiled<C>(a, P, gpar.data());
+    else
+      for (int c = 0; c < (int)nc; ++c) adj_collide_cell<C>(a, P, c, gpar.data());
     // the tiled gather of the GPU kernel on every third step, the plain one
     // otherwise: both are checked
     if (s % 3 == 2)

@@ -187,6 +187,7 @@ inline AdjBufLayout make_adj_layout(const lbf_params* P, const Layout& F) {
   // The tiled gather's grid: 128-cell rows and chunks of at least two
   // layers (2D), at most ceil(nx / 128) * ceil(nwn / 2) blocks.
   const long long nwn = P->dim == 3 ? P->nz : P->ny;
+  // the tiled passes: 128-cell rows, chunks of at least two layers
   const long long tiles = ((long long)(P->nx + 127) / 128) * ((nwn + 1) / 2);
   A.nblocks = (int)(tiles > A.cblocks ? tiles : A.cblocks);
   A.nwork = adj_nwork(P->nphase, P->dim);
