@@ -1,8 +1,9 @@
 // HIP kernels of the reverse (adjoint) step and their launchers.
 //
 //   adj_moment_kernel        pass 1: forward moments of x^n
-//   adj_collide_tile_kernel  pass 2: reverse of the collide pass (row tiles
-//                            marching the wall-normal axis, LDS ring)
+//   adj_collide_*kernel      pass 2: reverse of the collide pass (N >= 3: row
+//                            tiles marching the wall-normal axis with an LDS
+//                            ring; N <= 2: one thread per cell)
 //   adj_gather_kernel        pass 3: transpose of the finite differences and
 //                            of the moments (SEED: start from the objective)
 //   adj_objective_kernel     sums A = sum f_s psi, B = sum psi of a state
@@ -155,6 +156,25 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
   sa.nblocks = nblocks;
   const int t = xcd_remap(blockIdx.x, nblocks);
   gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, part + (long long)t * NPAR);
+}
+
+// Which form the collide reverse takes: for N >= 3 the tiled layer march
+// below (fewer live registers than reading every neighbour's fields from
+// global memory); for N <= 2 one thread per cell, which fits in 256 VGPRs
+// without spilling where the tiled form spills.  The batched kernels follow
+// the same rule, so batched and single-case sweeps stay bitwise equal.
+constexpr bool collide_reverse_tiled(int NP) { return NP >= 3; }
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+    adj_collide_kernel(AdjArgs<C> a, const KParams* __restrict__ kp, double* __restrict__ part) {
+  const KParams& P = *kp;
+  double g[NPAR];
+#pragma unroll
+  for (int k = 0; k < NPAR; ++k) g[k] = 0.0;
+  const int cell = blockIdx.x * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
+  block_sum<NPAR, true>(g, part);
 }
 
 // The collide reverse with its neighbour fields (phi_p, f_s, rho, u^{n-1}
@@ -315,6 +335,11 @@ inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* 
   switch (pass) {
     case 0: hipLaunchKernelGGL((adj_moment_kernel<C>), grid, block, 0, s, a, dP); break;
     case 1:
+      if constexpr (!collide_reverse_tiled(NP)) {
+        hipLaunchKernelGGL((adj_collide_kernel<C>), grid, block, 0, s, a, dP, part);
+        break;
+      }
+      [[fallthrough]];
     case 2: {
       // the gradient rows of the buffer layout assume 128-cell rows and
       // chunks of at least two layers in 2D

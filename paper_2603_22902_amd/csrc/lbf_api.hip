@@ -1217,7 +1217,8 @@ lbf_status lbf_batch_adjoint_step(lbf_batch_adj* ba, const void* state, const vo
     const lbf_batch_adj::Group& G = ba->g[gi];
     if (!G.n) continue;
     const lbf::Ops* ops = b->g[gi].ctx[0]->ops;
-    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, b->stream),
+    const int nb0 = lbf::collide_reverse_tiled(gi + 1) ? G.tblocks : G.cblocks;
+    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, nb0, state, next, ba->cur, b->stream),
            "batched collide reverse");
     HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, b->stream),
            "batched gather");

@@ -25,7 +25,7 @@ struct BatchAdjCase {
   void* la[2];
   void* work;
   double* part;                       // gradient rows of the case
-  int cblocks, first_cblock;          // one-thread-per-cell grid (unused by the tiled passes)
+  int cblocks, first_cblock;          // one-thread-per-cell grid (collide reverse for N <= 2)
   int ntx, nty, chunk, nblocks;       // tile geometry of both passes (single-case step geometry)
   int first_tblock;
 };
@@ -60,6 +60,23 @@ __device__ inline AdjArgs<C> batch_adj_args(const BatchAdjCase& bc, const char* 
   a.laout = static_cast<S*>(bc.la[1 - parity]);
   a.work = static_cast<typename C::R*>(bc.work);
   return a;
+}
+
+template <class C>
+__global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+    batch_adj_collide_cell_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
+                                  const char* __restrict__ state, const char* __restrict__ next, int parity) {
+  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, blockIdx.x, true));
+  const BatchAdjCase& bc = cs[k];
+  const KParams& P = kpa[k];
+  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
+  double g[NPAR];
+#pragma unroll
+  for (int j = 0; j < NPAR; ++j) g[j] = 0.0;
+  const int lb = blockIdx.x - bc.first_cblock;
+  const int cell = lb * ADJ_THREADS + threadIdx.x;
+  if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
+  block_sum_to<NPAR, true>(g, bc.part + (long long)lb * NPAR);
 }
 
 template <class C>
@@ -98,8 +115,9 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
   gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, bc.part + (long long)t * NPAR);
 }
 
-// pass 0: collide reverse, 1: tiled gather, both over the cases' tiles
-// (nblocks in all).  cases: the case table followed, at the next 256-byte
+// pass 0: collide reverse (over the cases' tiles for N >= 3, their 256-cell
+// blocks for N <= 2), 1: tiled gather over the cases' tiles; nblocks in
+// all.  cases: the case table followed, at the next 256-byte
 // boundary, by the cases' parameter blocks in table order, which the kernels
 // read through a restrict pointer (scalar loads, no LDS copy).
 inline size_t batch_adj_params_offset(int ncase) {
@@ -116,7 +134,10 @@ inline hipError_t launch_batch_adjoint(int pass, const void* cases, int ncase, i
   const char* st = static_cast<const char*>(state);
   const char* nx = static_cast<const char*>(next);
   if (!st || !nx || nblocks < 1) return hipErrorInvalidValue;
-  if (pass == 0)
+  if (pass == 0 && !collide_reverse_tiled(NP))
+    hipLaunchKernelGGL((batch_adj_collide_cell_kernel<C>), dim3(nblocks), dim3(ADJ_THREADS), 0, s, cs, kpa, ncase,
+                       st, nx, parity);
+  else if (pass == 0)
     hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
                        nx, parity);
   else if (pass == 1)
