@@ -4,19 +4,22 @@
 //   adj_collide_*kernel      pass 2: reverse of the collide pass (N >= 3: row
 //                            tiles marching the wall-normal axis with an LDS
 //                            ring; N <= 2: one thread per cell)
-//   adj_gather_kernel        pass 3: transpose of the finite differences and
-//                            of the moments (SEED: start from the objective)
+//   adj_gather_*kernel       pass 3: transpose of the finite differences and
+//                            of the moments (tiled like the collide reverse;
+//                            the seed pass, one thread per cell, starts from
+//                            the objective)
 //   adj_objective_kernel     sums A = sum f_s psi, B = sum psi of a state
 //   adj_seed_kernel          adjoints of phi, f_s of the objective
 //   adj_init_latent_kernel   dependence of the initial state on L_p
 //
 // (The block partials are summed into the gradient by a kernel of the API
 // unit, which does not depend on the precision.)
-// One thread per cell, 256-thread blocks.  Each thread's parameter-gradient
-// contributions are summed in a fixed order (wave shuffles, then waves) and
-// added to its block's row of a running accumulator; the rows are reduced
-// once, in block order, when the gradient is read.  A reverse run is thus
-// deterministic.
+// The per-cell kernels use 256-thread blocks; the tiled ones one 128-cell row
+// of a tile per block.  Each thread's parameter-gradient contributions are
+// summed in a fixed order (wave shuffles, then waves) and added to its
+// block's row of a running accumulator (rows by block, or by tile for the
+// tiled kernels); the rows are reduced once, in row order, when the gradient
+// is read.  A reverse run is thus deterministic.
 #pragma once
 
 #include <hip/hip_runtime.h>
