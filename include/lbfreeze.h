@@ -187,9 +187,10 @@ lbf_status lbf_state_from_device(lbf_ctx* ctx, const void* src, long long steps)
 lbf_status lbf_step_states(lbf_ctx* ctx, const void* src, void* dst);
 
 /* ---- Reverse mode: the discrete adjoint of the Sec. 3 step ----------------
- * Gradient of the frozen fraction of the freezing material at the final
- * state, J = sum_x f_s psi / sum_x psi (psi = sum of the freezing phases'
- * phi_p, f_s and phi_p the moments of the final state), with respect to
+ * Gradient of an objective of the final state (lbf_adjoint_seed_objective:
+ * the frozen fraction of the freezing material, J = sum_x f_s psi / sum_x psi
+ * with psi the sum of the freezing phases' phi_p, or the front position),
+ * f_s and phi_p the moments of the final state, with respect to
  * T_face[2], latent[4] and cos_theta[4][4] (each entry independent), through
  * every step of the run and the equilibrium start (lbf_init_fields with u
  * and p zero).  Built for dim = 2 with LBF_FP32 or LBF_FP64 (LBF_ENOTSUP
@@ -200,8 +201,9 @@ lbf_status lbf_step_states(lbf_ctx* ctx, const void* src, void* dst);
  * Use: run the forward steps keeping device states x^0..x^K (or checkpoints
  * and recomputation); with x^K current, lbf_adjoint_seed; then for
  * n = K-1 .. 0, lbf_adjoint_step with x^n (and x^{n+1}); then
- * lbf_adjoint_finish with x^0 and lbf_adjoint_gradient.  All calls are asynchronous on the context's
- * stream except seed and gradient, which synchronise it.  The adjoint
+ * lbf_adjoint_finish with x^0 and lbf_adjoint_gradient.  All calls are
+ * asynchronous on the context's stream except seed and gradient, which
+ * synchronise it.  The adjoint
  * context reads the forward context's parameters and stream; it must not
  * outlive it.  The caller allocates lbf_adjoint_bytes of device memory
  * (256-byte aligned) and keeps it for the adjoint context's lifetime. */
