@@ -24,7 +24,7 @@ import ctypes
 
 import numpy as np
 
-from .lbfreeze import LBF_OK, LbfError, Solver, _PD, _ptr, lib, make_params
+from .lbfreeze import LBF_OK, LbfError, Solver, _ptr, lib, make_params
 
 NPAR = 22
 OBJECTIVES = {"frozen_fraction": 0, "front": 1}
