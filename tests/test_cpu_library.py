@@ -126,3 +126,38 @@ def test_float32_liquid_fraction_metric_is_well_conditioned():
     assert T0 == T1 == 0.0
     assert abs(fl1 - fl0) > 10 * TOL["fp32"]
     assert abs(psi * fl1 - psi * fl0) <= 2e-7
+
+
+def test_entry_points_refuse_bad_arguments_before_any_device_work():
+    """Argument checks run on the host, first: NULL handles and outputs, bad
+    buffers and sizes give LBF_EINVAL without touching a device."""
+    import ctypes
+
+    L = lbfreeze.lib()
+    E = lbfreeze.LBF_EINVAL
+    n = ctypes.c_size_t(0)
+    d = ctypes.c_double(0.0)
+    assert L.lbf_batch_state_bytes(None, ctypes.byref(n)) == E
+    assert L.lbf_batch_state_to_device(None, None) == E
+    assert L.lbf_batch_step_states(None, None, None) == E
+    assert L.lbf_batch_adjoint_bytes(None, ctypes.byref(n)) == E
+    assert L.lbf_batch_adjoint_create(None, None, 0, None) == E
+    assert L.lbf_batch_adjoint_seed(None, 0, None, None) == E
+    assert L.lbf_batch_adjoint_step(None, None, None) == E
+    assert L.lbf_batch_adjoint_finish(None, None) == E
+    assert L.lbf_batch_adjoint_gradient(None, None) == E
+    assert L.lbf_adjoint_seed_objective(None, 0, None) == E
+    assert L.lbf_adjoint_step(None, None, None) == E
+    # the bandwidth probe: NULL, aliased, too small, unaligned, no outputs
+    buf = ctypes.create_string_buffer(1 << 16)
+    a = ctypes.addressof(buf)
+    pd = ctypes.pointer(d)
+    assert L.lbf_bandwidth_probe(None, None, 1 << 15, None, 1, pd, pd) == E
+    assert L.lbf_bandwidth_probe(ctypes.c_void_p(a), ctypes.c_void_p(a), 1 << 15, None, 1, pd, pd) == E
+    assert L.lbf_bandwidth_probe(ctypes.c_void_p(a), ctypes.c_void_p(a + (1 << 15)), 64, None, 1, pd, pd) == E
+    assert L.lbf_bandwidth_probe(ctypes.c_void_p(a + 4), ctypes.c_void_p(a + (1 << 15)), 1 << 12, None, 1,
+                                 pd, pd) == E
+    assert L.lbf_bandwidth_probe(ctypes.c_void_p(a), ctypes.c_void_p(a + (1 << 15)), 1 << 12, None, 0,
+                                 pd, pd) == E
+    assert L.lbf_bandwidth_probe(ctypes.c_void_p(a), ctypes.c_void_p(a + (1 << 15)), 1 << 12, None, 1,
+                                 None, pd) == E
