@@ -169,6 +169,17 @@ def tape_bytes(solver: Solver, nsteps: int) -> int:
     return (nsteps + 1) * solver.state_device_bytes()
 
 
+def choose_window(solver: Solver, nsteps: int, window=None) -> int:
+    """window as given, else 0 (the whole trajectory in a device tape, no
+    recomputation) when that tape fits in half the free device memory, else
+    checkpoints every 50 steps."""
+    if window is not None:
+        return int(window)
+    import torch
+    free, _ = torch.cuda.mem_get_info(solver.device)
+    return 0 if tape_bytes(solver, nsteps) < 0.5 * free else 50
+
+
 def forward_to_tape(solver: Solver, case: dict, nsteps: int):
     """Equilibrium start from case, then nsteps steps written straight into
     a device tape (row j = x^j, nsteps + 1 rows, no copies); the solver's
@@ -229,12 +240,14 @@ def case_with(case: dict, T_w=None, latent=None, cos_theta=None) -> dict:
     return c
 
 
-def frozen_fraction_and_gradient(case: dict, nsteps: int, window: int = 50, device: int = 0,
+def frozen_fraction_and_gradient(case: dict, nsteps: int, window=None, device: int = 0,
                                  objective: str = "frozen_fraction"):
     """Forward run with checkpoints, then the reverse sweep: (J, gradient)
     of the objective ("frozen_fraction" or "front").  window = 0 keeps the
-    whole trajectory on the device (no recomputation)."""
+    whole trajectory on the device (no recomputation); None chooses that
+    when it fits (choose_window)."""
     s = Solver(case["params"], device=device)
+    window = choose_window(s, nsteps, window)
     if window == 0:
         tape = forward_to_tape(s, case, nsteps)
         J, g = reverse_from_tape(s, tape, nsteps, objective=objective)
@@ -259,6 +272,7 @@ def _torch_function():
             c = case_with(case, float(T_w), latent.detach().cpu().numpy(),
                           cos_theta.detach().cpu().numpy())
             s = Solver(c["params"], device=device)
+            window = choose_window(s, nsteps, window)
             ck = forward_to_tape(s, c, nsteps) if window == 0 else forward_with_checkpoints(s, c, nsteps, window)
             d = s.lbf_diagnostics()
             N = s.N
@@ -291,7 +305,7 @@ def _torch_function():
 _FF = None
 
 
-def frozen_fraction(T_w, latent, cos_theta, case: dict, nsteps: int, window: int = 50, device: int = 0):
+def frozen_fraction(T_w, latent, cos_theta, case: dict, nsteps: int, window=None, device: int = 0):
     """torch entry point: the frozen fraction J(T_w, latent, cos_theta) with
     autograd support."""
     global _FF
@@ -300,7 +314,7 @@ def frozen_fraction(T_w, latent, cos_theta, case: dict, nsteps: int, window: int
     return _FF.apply(T_w, latent, cos_theta, case, nsteps, window, device, "frozen_fraction")
 
 
-def front_position(T_w, latent, cos_theta, case: dict, nsteps: int, window: int = 50, device: int = 0):
+def front_position(T_w, latent, cos_theta, case: dict, nsteps: int, window=None, device: int = 0):
     """torch entry point: the front position s(T_w, latent, cos_theta) =
     sum f_s psi / (cells per wall layer) with autograd support."""
     global _FF

@@ -83,6 +83,20 @@ def test_full_tape_equals_checkpointed_gradient(objective):
     assert J0 == J1 and np.array_equal(g0["raw"], g1["raw"])
 
 
+def test_automatic_window_chooses_the_full_tape_when_it_fits():
+    """window = None keeps a small run's whole trajectory on the device and
+    gives the checkpointed gradient bitwise."""
+    from paper_2603_22902_amd import Solver
+    from paper_2603_22902_amd.adjoint import choose_window
+    case = make_case(*CASES[0], precision="fp32")
+    s = Solver(case["params"])
+    assert choose_window(s, 25) == 0 and choose_window(s, 25, 7) == 7
+    s.close()
+    J0, g0 = _grad(case, 25, 7)
+    J1, g1 = _grad(case, 25, None)
+    assert J0 == J1 and np.array_equal(g0["raw"], g1["raw"])
+
+
 def test_float32_adjoint_close_to_float64():
     """float32 storage and arithmetic: the gradient of the same case within
     1e-3 relative of the float64 one (measured ~1e-5)."""
