@@ -187,3 +187,28 @@ def test_impurities_workload_full_length_is_stable():
         front = d["front"]
         assert np.all(np.abs(drift[:3]) < 2e-3), drift
     assert front > 2.0
+
+
+@pytest.mark.parametrize("workload,nsteps,drift_bar,sumphi_bar", [
+    ("droplet", 20000, 5e-3, 1e-2),    # 256^2 D2Q9 N = 2
+    ("compound", 500, 3e-3, 5e-2),     # 512^2 D2Q9 N = 3 (the adjoint's run)
+])
+def test_2d_workloads_full_length_are_stable(workload, nsteps, drift_bar, sumphi_bar):
+    """The 2D workloads for their full runs in float32: finite, the front
+    rising monotonically, sum_p phi_p near 1 and every phase mass within the
+    bar of its start, checked ten times along the run."""
+    from paper_2603_22902_amd import Solver
+    c = synth.WORKLOADS[workload]()
+    s = Solver(c["params"])
+    s.init_case(c)
+    m0 = s.lbf_diagnostics()["mass"]
+    front = 0.0
+    for k in range(10):
+        s.lbf_step(nsteps // 10)
+        d = s.lbf_diagnostics()
+        drift = (d["mass"] - m0) / m0
+        print(workload, "step", nsteps // 10 * (k + 1), "front", d["front"], "drift", drift, flush=True)
+        assert not d["nonfinite"] and d["max_sum_phi_err"] < sumphi_bar
+        assert d["front"] > front
+        front = d["front"]
+        assert np.all(np.abs(drift) < drift_bar), drift
