@@ -4,9 +4,10 @@
 // cases' first block numbers) and runs the single-case phase functions with
 // the case's parameter block, read through a restrict pointer into a
 // contiguous array of the group's blocks (scalar loads, as in the
-// single-case kernels).  Each case keeps the tile decomposition and the
-// gradient rows of its single-case reverse step, so its gradient is bitwise
-// the one a single-case sweep gives.
+// single-case kernels).  Each case keeps the block decomposition (tiles, or
+// 256-cell blocks for the per-cell collide reverse) and the gradient rows of
+// its single-case reverse step, so its gradient is bitwise the one a
+// single-case sweep gives.
 #pragma once
 
 #include <hip/hip_runtime.h>
