@@ -219,6 +219,10 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
             "reverse_step_ms": round(t["reverse_ms"] / nsteps, 4),
             "forward_step_ms": round(step_ms, 4),
             "ratio_no_recompute": round(t["reverse_ms"] / nsteps / step_ms, 3),
+            # what the library's default (window=None) takes at this size:
+            # the full tape when it fits in half the free memory
+            "default_window": "full tape" if full else window,
+            "ratio_default_window": full["ratio_vs_plain_forward"] if full else round(bwd / fwd, 3),
             "full_tape": full,
             "J": J, "dJ_dTw": float(dJ_dTw), "dJ_dSte": float(dJ_dSte)}
 
