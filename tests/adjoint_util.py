@@ -19,6 +19,17 @@ CASES = [
     (3, ("wall", "open"), ("dirichlet", "dirichlet"), 70.0),
 ]
 
+# One phase (no interface terms) and four phases (the largest per-cell
+# reverse state, tiled collide reverse).  Central differences of these take
+# steps ten times those of checks(): the fourth phase's wetting entries are
+# ~1e-3 of the largest, and over 30 steps the rounding of J / h with the
+# smaller steps reaches 1e-10 (measured: h = 1e-6 misses the 1e-6 relative
+# bar on them; h = 1e-5 meets it on every entry).
+CASES_N14 = [
+    (1, ("wall", "wall"), ("dirichlet", "adiabatic"), 70.0),
+    (4, ("wall", "open"), ("dirichlet", "dirichlet"), 70.0),
+]
+
 
 def make_case(N, fbc, tbc, theta, precision="fp64", shape=(20, 12)):
     c = synth.small(dim=2, shape=shape, nphase=N, precision=precision, flow_bc=fbc, therm_bc=tbc,

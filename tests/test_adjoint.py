@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import emulator
-from adjoint_util import CASES, central, checks, make_case, oracle_front, oracle_J
+from adjoint_util import CASES, CASES_N14, central, checks, make_case, oracle_front, oracle_J
 
 pytestmark = pytest.mark.skipif(not emulator.available(), reason="emulator not built")
 
@@ -79,6 +79,41 @@ def test_emulated_front_gradient_matches_oracle():
     J, g = emulator.adjoint(prm, case["phi"], case["T"], n, objective="front")
     assert abs(J - oracle_front(case, prm, n)) <= 1e-12 * max(1.0, J)
     fj = lambda q: oracle_front(case, q, n)
+    for key, idx, h, pick in checks(prm):
+        fd = central(fj, prm, key, idx, h)
+        assert abs(pick(g) - fd) <= 1e-4 * abs(fd) + 1e-10, (key, idx, pick(g), fd)
+
+
+@pytest.mark.parametrize("spec", CASES_N14, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
+@pytest.mark.parametrize("nsteps", [6, 30])
+def test_emulated_adjoint_one_and_four_phases(spec, nsteps):
+    """N = 1 and N = 4: the reverse sweep against central differences of the
+    same forward step (steps ten times those of checks(), see CASES_N14),
+    at the 1e-6 relative bar."""
+    case = make_case(*spec)
+    prm = case["params"]
+    J, g = emulator.adjoint(prm, case["phi"], case["T"], nsteps)
+    assert 0.0 < J < 1.0
+    fj = lambda q: emulator.adjoint(q, case["phi"], case["T"], nsteps)[0]
+    scale = max(abs(g[k]) for k in range(22))
+    for key, idx, h, pick in checks(prm):
+        fd = central(fj, prm, key, idx, 10.0 * h)
+        assert abs(pick(g) - fd) <= 1e-6 * abs(fd) + 1e-9 * scale, (key, idx, pick(g), fd)
+
+
+@pytest.mark.parametrize("spec", CASES_N14, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
+def test_emulated_adjoint_one_and_four_phases_match_oracle(spec):
+    """N = 1 and N = 4: J of both objectives equals the FP64 oracle's, and the
+    frozen fraction's gradient meets the oracle's central differences within
+    1e-4."""
+    case = make_case(*spec)
+    prm = case["params"]
+    n = 20
+    J, g = emulator.adjoint(prm, case["phi"], case["T"], n)
+    assert abs(J - oracle_J(case, prm, n)) <= 1e-12
+    Jf, _ = emulator.adjoint(prm, case["phi"], case["T"], n, objective="front")
+    assert abs(Jf - oracle_front(case, prm, n)) <= 1e-12 * max(1.0, Jf)
+    fj = lambda q: oracle_J(case, q, n)
     for key, idx, h, pick in checks(prm):
         fd = central(fj, prm, key, idx, h)
         assert abs(pick(g) - fd) <= 1e-4 * abs(fd) + 1e-10, (key, idx, pick(g), fd)

@@ -9,7 +9,7 @@ import pytest
 
 import emulator
 import synth
-from adjoint_util import CASES, central, checks, make_case, oracle_front, oracle_J
+from adjoint_util import CASES, CASES_N14, central, checks, make_case, oracle_front, oracle_J
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +19,7 @@ def _grad(case, nsteps, window, objective="frozen_fraction"):
     return frozen_fraction_and_gradient(case, nsteps, window, objective=objective)
 
 
-@pytest.mark.parametrize("spec", CASES, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
+@pytest.mark.parametrize("spec", CASES + CASES_N14, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
 def test_gpu_adjoint_matches_emulator_fp64(spec):
     case = make_case(*spec)
     print("adjoint case", spec, flush=True)
@@ -108,6 +108,20 @@ def test_float32_adjoint_close_to_float64():
     err = np.abs(g32["raw"] - g64["raw"]).max() / scale
     print("fp32 vs fp64 gradient", err)
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("spec", CASES_N14, ids=lambda s: f"N{s[0]}_{s[1][1]}_{s[2][1]}")
+def test_float32_adjoint_close_to_float64_one_and_four_phases(spec):
+    """The same bar for N = 1 (per-cell collide reverse) and N = 4 (tiled),
+    both objectives."""
+    for objective in ("frozen_fraction", "front"):
+        print("fp32 adjoint", spec, objective, flush=True)
+        _, g64 = _grad(make_case(*spec), 30, 10, objective)
+        _, g32 = _grad(make_case(*spec, precision="fp32"), 30, 10, objective)
+        scale = np.abs(g64["raw"]).max()
+        err = np.abs(g32["raw"] - g64["raw"]).max() / scale
+        print("fp32 vs fp64 gradient", err)
+        assert err <= 1e-3
 
 
 @pytest.mark.parametrize("objective", ["frozen_fraction", "front"])
