@@ -5,6 +5,8 @@
   liblbfreeze_emu.so   host emulator of the step and reverse-step kernels
                        (CPU tests only)
   lbf_emu_sanitize     sanitizer driver of the emulator (CPU tests only)
+  lbf_emu_adj_sanitize sanitizer driver of the emulated reverse step (CPU
+                       tests only)
 
 Usage: ``python -m paper_2603_22902_amd.build`` or ``build()``.  Every call
 recompiles.  The kernels are compiled with packed-fp32 instructions
@@ -25,6 +27,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblbfreeze.so")
 EMU = os.path.join(HERE, "liblbfreeze_emu.so")
 EMU_SAN = os.path.join(HERE, "lbf_emu_sanitize")
+EMU_ADJ_SAN = os.path.join(HERE, "lbf_emu_adj_sanitize")
 ARCH = "gfx950"
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -59,6 +62,11 @@ def build(verbose: bool = False, emulator: bool = True) -> str:
                          "-Xarch_host", "-fsanitize=undefined",
                          "-fno-omit-frame-pointer", os.path.join(CSRC, "lbf_emu.hip"),
                          "-o", EMU_SAN + ".tmp"])
+            jobs.append([HIPCC, *HOST_FLAGS, "-O1", "-g", "-DLBF_EMU_ADJ_MAIN",
+                         "-Xarch_host", "-fsanitize=address",
+                         "-Xarch_host", "-fsanitize=undefined",
+                         "-fno-omit-frame-pointer", os.path.join(CSRC, "lbf_emu_adj.hip"),
+                         "-o", EMU_ADJ_SAN + ".tmp"])
         with ThreadPoolExecutor(max_workers=min(len(jobs), 6)) as ex:
             list(ex.map(lambda c: _run(c, verbose), jobs))
         _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"], verbose)
@@ -66,6 +74,7 @@ def build(verbose: bool = False, emulator: bool = True) -> str:
         if emulator:
             os.replace(EMU + ".tmp", EMU)
             os.replace(EMU_SAN + ".tmp", EMU_SAN)
+            os.replace(EMU_ADJ_SAN + ".tmp", EMU_ADJ_SAN)
     return LIB
 
 

@@ -253,3 +253,96 @@ extern "C" int lbf_emu_adjoint(const lbf_params* prm, const double* phi, const d
   if (q.dim == 3 && q.precision == LBF_FP32) return run_n<3, float, float>(&q, phi, T, nsteps, objective, J, grad);
   return -2;
 }
+
+#ifdef LBF_EMU_ADJ_MAIN
+#include <stdio.h>
+
+// Sanitizer driver of the reverse step: 2D, every phase count, float64 and
+// float32, three face combinations, the frozen-fraction and front objectives
+// in turn, on a narrow grid and on one that spans two 128-wide row tiles.
+// Four steps reach the per-cell and both tiled forms of the passes.  The
+// start has separated phases (a droplet with a core and, for N = 4, a
+// bubble): where two phases are mixed in bulk, the pairwise normal is
+// rounding noise and its exact derivative overflows float32.  Exit status 0
+// when every J and gradient stays finite.
+int main() {
+  int bad = 0, runs = 0;
+  const int shapes[2][2] = {{37, 11}, {150, 21}};
+  for (int sh = 0; sh < 2; ++sh)
+    for (int N = 1; N <= 4; ++N)
+      for (int prec = 0; prec < 2; ++prec)
+        for (int bcase = 0; bcase < 3; ++bcase) {
+          const int obj = (N + prec + bcase) % 2 ? LBF_OBJ_FRONT : LBF_OBJ_FROZEN_FRACTION;
+          lbf_params P;
+          memset(&P, 0, sizeof P);
+          P.dim = 2;
+          P.nx = shapes[sh][0];
+          P.ny = shapes[sh][1];
+          P.nz = 1;
+          P.nphase = N;
+          P.precision = prec == 0 ? LBF_FP64 : LBF_FP32;
+          P.flow_bc[0] = LBF_BC_WALL;
+          P.flow_bc[1] = bcase == 1 ? LBF_BC_OPEN : LBF_BC_WALL;
+          P.therm_bc[0] = LBF_TBC_DIRICHLET;
+          P.therm_bc[1] = bcase == 2 ? LBF_TBC_DIRICHLET : LBF_TBC_ADIABATIC;
+          P.T_face[0] = -0.05;
+          P.T_face[1] = 0.05;
+          for (int p = 0; p < N; ++p) {
+            const bool fr = (p % 2) == 0;
+            P.rho_l[p] = fr ? 1.0 : 0.01 * (p + 1);
+            P.rho_s[p] = fr ? 0.9 + 0.1 * p : P.rho_l[p];
+            P.mu_l[p] = 0.1 * P.rho_l[p];
+            P.mu_s[p] = 0.1 * P.rho_s[p];
+            P.lam_l[p] = P.lam_s[p] = 0.1;
+            P.cp_l[p] = P.cp_s[p] = fr ? 1.0 : 1.0 / P.rho_l[p];
+            P.latent[p] = fr ? 1.0 : 0.0;
+            P.freezes[p] = fr ? 1 : 0;
+            for (int q = 0; q < N; ++q) {
+              P.sigma[p][q] = p == q ? 0.0 : 1e-3;
+              P.cos_theta[p][q] = p < q ? 0.3 : (p > q ? -0.3 : 0.0);
+            }
+          }
+          P.eps = 4;
+          P.tau_g = 0.8;
+          P.T_melt = 0;
+          P.E_ref = 1;
+          const long long nc = (long long)P.nx * P.ny;
+          std::vector<double> phi((size_t)N * nc), T(nc);
+          for (long long c = 0; c < nc; ++c) {
+            const int x = c % P.nx, y = c / P.nx;
+            const double r = sqrt((x - 18.0) * (x - 18.0) + (double)y * y);
+            const double d = 0.5 + 0.5 * tanh((8.0 - r) / 2.0);
+            const double core = 0.5 + 0.5 * tanh((4.0 - r) / 2.0);
+            const double rb = sqrt((x - 30.0) * (x - 30.0) + (y - 7.0) * (y - 7.0));
+            const double bub = N == 4 ? 0.5 + 0.5 * tanh((2.5 - rb) / 2.0) : 0.0;
+            double part[4] = {1.0, 0.0, 0.0, 0.0};
+            if (N == 2) {
+              part[0] = d;
+              part[1] = 1.0 - d;
+            } else if (N >= 3) {
+              part[0] = d * (1.0 - core);
+              part[1] = 1.0 - d;
+              part[2] = d * core;
+            }
+            if (N == 4) {
+              for (int p = 0; p < 3; ++p) part[p] *= 1.0 - bub;
+              part[3] = bub;
+            }
+            for (int p = 0; p < N; ++p) phi[(size_t)p * nc + c] = part[p];
+            T[c] = 0.005 + 0.002 * y;  // just above melting, cold wall below
+          }
+          double J = 0.0, g[22];
+          const int rc = lbf_emu_adjoint(&P, phi.data(), T.data(), 4, obj, &J, g);
+          ++runs;
+          bool ok = rc == 0 && isfinite(J);
+          for (double v : g) ok = ok && isfinite(v);
+          if (!ok) {
+            printf("non-finite or refused: %dx%d N=%d prec=%d bc=%d obj=%d rc=%d\n", P.nx, P.ny, N, prec, bcase,
+                   obj, rc);
+            ++bad;
+          }
+        }
+  printf("%d runs, %d with non-finite output\n", runs, bad);
+  return bad ? 1 : 0;
+}
+#endif

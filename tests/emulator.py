@@ -12,6 +12,7 @@ from paper_2603_22902_amd import lbfreeze
 
 EMU_PATH = os.path.join(os.path.dirname(lbfreeze.LIB_PATH), "liblbfreeze_emu.so")
 SAN_PATH = os.path.join(os.path.dirname(lbfreeze.LIB_PATH), "lbf_emu_sanitize")
+ADJ_SAN_PATH = os.path.join(os.path.dirname(lbfreeze.LIB_PATH), "lbf_emu_adj_sanitize")
 _PD = ctypes.POINTER(ctypes.c_double)
 _emu = None
 

@@ -103,9 +103,22 @@ def test_emulated_kernel_matches_oracle(spec):
 
 @pytest.mark.skipif(not os.path.exists(emulator.SAN_PATH), reason="sanitizer driver not built")
 def test_emulated_kernel_under_address_sanitizer():
-    r = subprocess.run([emulator.SAN_PATH], capture_output=True, text=True, timeout=600)
+    r = subprocess.run([emulator.SAN_PATH], capture_output=True, text=True, timeout=600,
+                       env={**os.environ, "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"})
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     assert "0 with non-finite output" in r.stdout
+
+
+@pytest.mark.skipif(not os.path.exists(emulator.ADJ_SAN_PATH), reason="sanitizer driver not built")
+def test_emulated_reverse_step_under_address_sanitizer():
+    """The reverse step's passes (per-cell and tiled forms) on the host under
+    AddressSanitizer and UBSan: 2D, N = 1..4, float64 and float32, three
+    face combinations, both objectives, grids narrower than one row tile and
+    spanning two; every J and gradient finite."""
+    r = subprocess.run([emulator.ADJ_SAN_PATH], capture_output=True, text=True, timeout=600,
+                       env={**os.environ, "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"})
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "48 runs, 0 with non-finite output" in r.stdout
 
 
 def test_float32_liquid_fraction_metric_is_well_conditioned():
