@@ -430,6 +430,28 @@ def main():
     print(f"[bench] moments {ms_mom * 1e3:.1f} us, collide {ms_col * 1e3:.1f} us per launch; "
           f"front {diag['front']:.4f} nonfinite {diag['nonfinite']}", file=sys.stderr, flush=True)
 
+    # The same K steps as a whole job through the host boundary (context,
+    # never the metric): float64 phi, T from host memory into the equilibrium
+    # start, the steps, and every moment back to float64 host memory.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.init_case(case)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.lbf_step(args.steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.lbf_get_moments()
+    t3 = time.perf_counter()
+    host_io = {"init_fields_ms": round((t1 - t0) * 1e3, 2), "steps_ms": round((t2 - t1) * 1e3, 2),
+               "get_moments_ms": round((t3 - t2) * 1e3, 2),
+               # float64 fields up (phi, T, u and p if given) and down (every moment)
+               "host_bytes": int(8 * ncell * (prm["nphase"] + 1 + (prm["dim"] if case.get("u") is not None else 0)
+                                              + (1 if case.get("p") is not None else 0)
+                                              + prm["nphase"] + prm["dim"] + 6)),
+               "mlups_with_host_io": round(ncell * args.steps / (t3 - t0) / 1e6, 1)}
+    print(f"[bench] with host I/O {host_io}", file=sys.stderr, flush=True)
+
     # same-box HBM rates of a plain float4 copy and read sweep, for context
     from paper_2603_22902_amd.lbfreeze import bandwidth_probe
     bw = bandwidth_probe(s.device)
@@ -458,6 +480,7 @@ def main():
                      "kernel": "collide_kernel", "kernel_us": round(ms_col * 1e3, 2),
                      "bytes_per_cell": bpc["collide"]},
         "bandwidth_probe": probe,
+        "host_io": host_io,
         "diagnostics": dlog,
         "kernels": {
             "moment_kernel": {"us": round(ms_mom * 1e3, 2), "bytes_per_cell": bpc["moments"],
