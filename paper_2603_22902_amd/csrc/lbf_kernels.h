@@ -365,12 +365,12 @@ inline Geometry step_geometry(const KParams& P) {
   g.ntx = (P.nx + C::TX - 1) / C::TX;
   g.nty = (C::DIM == 3) ? (P.ny + C::TY - 1) / C::TY : 1;
   const long long ntiles = (long long)g.ntx * g.nty;
-  // Aim for about 4096 blocks (many short chunks balance the CUs better than
-  // a few long ones); a chunk never drops below 4 layers in 3D and 2 in 2D
-  // (each chunk re-reads two extra layers).
-  const long long target = 4096;
+  // Aim for about 4608 blocks in 3D (18 per CU) and 4096 in 2D: many short
+  // chunks balance the CUs better than a few long ones.  A chunk never drops
+  // below 3 layers in 3D and 2 in 2D (each chunk re-reads two extra layers).
+  const long long target = (C::DIM == 3) ? 4608 : 4096;
   long long chunk = (P.nwn * ntiles + target - 1) / target;
-  const long long cmin = (C::DIM == 3) ? 4 : 2;
+  const long long cmin = (C::DIM == 3) ? 3 : 2;
   if (chunk < cmin) chunk = cmin;
   if (chunk > P.nwn) chunk = P.nwn;
   g.chunk = (int)chunk;
