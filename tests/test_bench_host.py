@@ -1,5 +1,6 @@
-"""Host logic of bench.py: the algorithmic bytes behind the roofline, and
-the committed counter traffic being tied to the current kernel sources."""
+"""Host logic of bench.py: the algorithmic bytes behind the roofline, the
+committed counter traffic being tied to the current kernel sources, and the
+refusal of more than one GPU."""
 import json
 import os
 
@@ -41,3 +42,14 @@ def test_committed_traffic_matches_the_current_kernel_sources():
     alg = bench.algorithmic_bytes_per_cell(3, 4, 4)["collide"] * 192 ** 3
     assert rec["algorithmic_bytes"] == alg
     assert 1.0 <= rec["bytes_per_launch"] / alg < 1.1
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """bench.py times one GPU only: --gpus above 1 exits with status 2 and
+    says why, before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
