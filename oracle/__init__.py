@@ -21,6 +21,11 @@ _LIB_PATH = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 WALL, OPEN = 0, 1
+# Readings of div u and of the volume source (see orc.c): DIV_MDOT takes
+# div u := mdot, DIV_LAGGED the central difference of u^{n-1}; MDOT_FREEZE
+# keeps the freezing term of eq. (fluid2) only, MDOT_PRINTED every printed term.
+DIV_MDOT, DIV_LAGGED = 0, 1
+MDOT_FREEZE, MDOT_PRINTED = 0, 1
 DIRICHLET, ADIABATIC = 0, 1
 _FLOW = {"wall": WALL, "open": OPEN}
 _THERM = {"dirichlet": DIRICHLET, "adiabatic": ADIABATIC}
@@ -64,6 +69,8 @@ def lib():
         L.orc_diagnostics.argtypes = [ctypes.c_void_p, _PD]
         L.orc_get_state.argtypes = [ctypes.c_void_p, _PD, _PD]
         L.orc_set_state.argtypes = [ctypes.c_void_p, _PD, _PD]
+        L.orc_set_readings.restype = ctypes.c_int
+        L.orc_set_readings.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         L.orc_threads.restype = ctypes.c_int
         L.orc_lattice.restype = ctypes.c_int
         L.orc_lattice.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _PD]
@@ -139,6 +146,13 @@ class Oracle:
         if h and _lib is not None:
             _lib.orc_destroy(h)
             self._h = None
+
+    def set_readings(self, div=None, mdot=None):
+        """Select the divergence and volume-source readings (DIV_*, MDOT_*)."""
+        d = DIV_LAGGED if div is None else div
+        m = MDOT_FREEZE if mdot is None else mdot
+        if lib().orc_set_readings(self._h, int(d), int(m)) != 0:
+            raise ValueError(f"unknown reading div={div} mdot={mdot}")
 
     def init(self, phi, T, u=None, p=None):
         phi = _f64(phi).reshape(self.N, self.ncell)

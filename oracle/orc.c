@@ -83,7 +83,19 @@ typedef struct {
   cellmac *mac;
   double *out_u, *out_p, *out_mdot; /* flow macros of the last pass */
   long step;
+  int div_mode;  /* ORC_DIV_*: what div u means in G_{i,p}, H_i and the moments */
+  int mdot_mode; /* ORC_MDOT_*: which terms of eq. (fluid2) form mdot        */
 } orc_state;
+
+/* Readings of two passages the paper leaves open, selectable so that the
+ * tests can run each of them.
+ *   ORC_DIV_MDOT:   div u := mdot, the continuity law eq. (fluid2).
+ *   ORC_DIV_LAGGED: the central difference of the previous step's u.
+ *   ORC_MDOT_FREEZE:  mdot = -(1/rho) sum_p (rho_p^s - rho_p^l) D(f_s phi_p)/Dt.
+ *   ORC_MDOT_PRINTED: the printed eq. (fluid2), which also carries
+ *                     -(1/rho) sum_p rho_p^l D phi_p/Dt. */
+enum { ORC_DIV_MDOT = 0, ORC_DIV_LAGGED = 1 };
+enum { ORC_MDOT_FREEZE = 0, ORC_MDOT_PRINTED = 1 };
 
 /* Lagged-field planes: phi_p^{n-1} (N), f_s^{n-1}, u^{n-1} (dim),
  * D^{n-1} (the velocity divergence used by the sources of step n-1), and
@@ -463,18 +475,12 @@ static void update_cell(orc_state *st, long c, int store) {
     stencil(L, d, Xn, gfsphi[p], NULL);
   }
 
-  /* Velocity divergence for the sources div u of G_{i,p}, H_i and the two
-   * moment corrections: the central difference of the previous step's
-   * velocity field u^{n-1} (the current u of the neighbours needs their
-   * forces, i.e. a second ring of cells).  Ghost velocities mirror the
-   * boundary cell at walls (zero velocity on the face) and copy it at open
-   * faces.  Taking div u from the velocity rather than from the continuity
-   * law keeps sum_p phi_p = 1 where the weakly compressible flow does not
-   * satisfy div u = mdot exactly, e.g. gas being compressed; with div u
-   * replaced by mdot that error grows without bound in gas at a 1000:1
-   * density ratio. */
+  /* The lagged-difference reading of div u (ORC_DIV_LAGGED): the central
+   * difference of the previous step's velocity field u^{n-1}.  Ghost
+   * velocities mirror the boundary cell at walls (zero velocity on the face)
+   * and copy it at open faces. */
   double Ddiv = 0.0;
-  {
+  if (st->div_mode == ORC_DIV_LAGGED) {
     const double *aux = st->aux;
     long nc = st->ncell;
     double ug[3] = {0, 0, 0};
@@ -516,17 +522,14 @@ static void update_cell(orc_state *st, long c, int store) {
     u[a] = ustar[a] + 0.5 * acc[a];
     rhoa[a] = m->rho * acc[a];
   }
-  /* Volume source of eq. (fluid2),
-   *   mdot = -(1/rho) sum_p (rho_p^s - rho_p^l) D(f_s phi_p)/Dt,
-   * with D X/Dt = (X^n - X^{n-1})/dt + u^n . grad X^n.  The printed source
-   * also carries sum_p rho_p^l D phi_p/Dt.  Each fluid is carried by the
-   * flow, so that term is zero in the continuum model.  Without phase change
-   * (rho_p^s = rho_p^l) this gives div u = 0, the incompressible N-phase model
-   * the method is said to reduce to.  In the discrete step the term is not
-   * zero inside diffuse interfaces.  There it is divided by the small
-   * gas-side mixture density, and through S it drives a pressure-velocity
-   * feedback.  At a 100:1 density ratio that feedback diverges within tens
-   * of steps even without freezing, so the term is left out. */
+  /* Volume source of eq. (fluid2), with D X/Dt = (X^n - X^{n-1})/dt +
+   * u^n . grad X^n.  Sec. 2 states that without phase change the flow is
+   * divergence free; the freezing term alone gives exactly that when
+   * rho_p^s = rho_p^l (ORC_MDOT_FREEZE):
+   *   mdot = -(1/rho) sum_p (rho_p^s - rho_p^l) D(f_s phi_p)/Dt.
+   * The printed source also carries sum_p rho_p^l D phi_p/Dt, which is not
+   * zero inside a diffuse interface even without freezing; ORC_MDOT_PRINTED
+   * keeps it. */
   const double *aux = st->aux;
   long nc = st->ncell;
   double fs_prev = aux[(long)AUX_FS(N) * nc + c];
@@ -539,9 +542,18 @@ static void update_cell(orc_state *st, long c, int store) {
       for (int a = 0; a < d; ++a) ug += u[a] * gfsphi[p][a];
       term += (P->rho_s[p] - P->rho_l[p]) * (m->fs * m->phi[p] - fs_prev * phi_prev + ug);
     }
+    if (st->mdot_mode == ORC_MDOT_PRINTED) {
+      double ug = 0.0;
+      for (int a = 0; a < d; ++a) ug += u[a] * gphi[p][a];
+      term += P->rho_l[p] * (m->phi[p] - phi_prev + ug);
+    }
     msum += term;
   }
   double mdot = -msum / m->rho;
+  /* The continuity reading of div u (ORC_DIV_MDOT): the sources of this
+   * step use mdot^n, the moments of the next step mdot^n as their lagged
+   * divergence. */
+  if (st->div_mode == ORC_DIV_MDOT) Ddiv = mdot;
   /* S = rho mdot + u . grad rho */
   double ugr = 0.0;
   for (int a = 0; a < d; ++a) ugr += u[a] * grho[a];
@@ -700,6 +712,8 @@ orc_state *orc_create(const orc_params *P) {
   st->ncell = (long)st->n[0] * st->n[1] * st->n[2];
   st->narea = st->ncell / st->n[st->wn];
   st->nlat = st->N + 2;
+  st->div_mode = ORC_DIV_LAGGED;
+  st->mdot_mode = ORC_MDOT_FREEZE;
   long np = (long)st->nlat * st->Q * st->ncell;
   long na = (long)NAUX(st->N, st->dim) * st->ncell;
   st->pop = (double *)calloc(np, sizeof(double));
@@ -729,6 +743,16 @@ void orc_destroy(orc_state *st) {
 }
 
 long orc_ncell(const orc_state *st) { return st->ncell; }
+
+/* Select the readings (ORC_DIV_*, ORC_MDOT_*); returns 0, or -1 if either
+ * value is unknown (the state is then unchanged). */
+int orc_set_readings(orc_state *st, int div_mode, int mdot_mode) {
+  if (div_mode != ORC_DIV_MDOT && div_mode != ORC_DIV_LAGGED) return -1;
+  if (mdot_mode != ORC_MDOT_FREEZE && mdot_mode != ORC_MDOT_PRINTED) return -1;
+  st->div_mode = div_mode;
+  st->mdot_mode = mdot_mode;
+  return 0;
+}
 int orc_q(const orc_state *st) { return st->Q; }
 int orc_naux(const orc_state *st) { return NAUX(st->N, st->dim); }
 long orc_step_count(const orc_state *st) { return st->step; }

@@ -103,6 +103,17 @@ def tanh_in(dist_inside, eps=EPS):
     return 0.5 + 0.5 * np.tanh(dist_inside / (eps / 2.0))
 
 
+def laplace_pressure(bodies, dim):
+    """Initial pressure of fluids at rest with curved interfaces: the
+    Young-Laplace jump sigma * (dim - 1) / R across the outer interface of
+    each round body, summed over nested bodies and smoothed by the bodies'
+    tanh indicators.  bodies = [(indicator, sigma, R), ...]."""
+    p = 0.0
+    for ind, sig, R in bodies:
+        p = p + sig * (dim - 1) / R * ind
+    return np.ascontiguousarray(p, dtype=np.float64)
+
+
 def _case(name, params, phi, T, steps, u=None, p=None):
     return dict(name=name, params=params, phi=np.ascontiguousarray(phi, dtype=np.float64),
                 T=np.ascontiguousarray(T, dtype=np.float64), u=u, p=p, steps=steps)
@@ -141,7 +152,7 @@ def droplet(seed_k=2, n=256, radius=60.0, steps=20000, precision="fp32",
     p1 = tanh_in(radius - r)
     phi = np.stack([p1, 1.0 - p1])
     T = np.full(p1.shape, T_HOT)
-    c = _case("droplet", prm, phi, T, steps)
+    c = _case("droplet", prm, phi, T, steps, p=laplace_pressure([(p1, 1e-3, radius)], 2))
     c["ste"] = ste
     return c
 
@@ -163,7 +174,8 @@ def compound(seed_k=3, n=512, r_core=60.0, r_shell=120.0, steps=500, precision="
     p2 = (1.0 - p1) * tanh_in(r_shell - r)
     phi = np.stack([p1, p2, 1.0 - p1 - p2])
     T = np.full(p1.shape, T_HOT)
-    return _case("compound", prm, phi, T, steps)
+    p = laplace_pressure([(p1 + p2, s23, r_shell), (p1, s12, r_core)], 2)
+    return _case("compound", prm, phi, T, steps, p=p)
 
 
 def impurities(seed_k=4, n=192, radius=64.0, steps=10000, precision="fp32"):
@@ -207,9 +219,29 @@ def impurities(seed_k=4, n=192, radius=64.0, steps=10000, precision="fp32"):
     rest = 1.0 - a - b
     phi = np.stack([rest * d, rest * (1.0 - d), a, b])
     T = np.full(d.shape, T_HOT)
-    c = _case("impurities", prm, phi, T, steps)
+    p = laplace_pressure([(d, 1e-3, radius), (a, 1e-3, rA), (b, 1e-3, rB)], 3)
+    c = _case("impurities", prm, phi, T, steps, p=p)
     c["impurity"] = dict(rA=rA, rB=rB, cA=cA.tolist(), cB=cB.tolist())
     return c
+
+
+def bubble(n=96, radius=10.0, rho_g=0.001, sigma=1e-3, inverted=False, laplace=True,
+           steps=500, precision="fp64"):
+    """A round gas bubble (or, inverted, a liquid drop in gas) at the centre
+    of a closed n x n box, no phase change (T above melting everywhere,
+    adiabatic walls).  The bubble is phase 2 (non-freezing, gas
+    properties), the liquid phase 1.  laplace=True starts from the
+    Young-Laplace pressure of the round interface."""
+    phases = [freezing_phase(ratio=0.9, lam=0.15, ste=0.1), inert_phase(rho_g, lam=0.15)]
+    prm = make_params(2, (n, n), phases, sigma=sigma, precision=precision,
+                      flow_bc=("wall", "wall"), therm_bc=("adiabatic", "adiabatic"),
+                      T_face=(T_HOT, T_HOT))
+    x, y, z = grid(prm)
+    b = tanh_in(radius - np.sqrt((x - n / 2) ** 2 + (y - n / 2) ** 2))
+    phi = np.stack([b, 1.0 - b]) if inverted else np.stack([1.0 - b, b])
+    T = np.full(b.shape, T_HOT)
+    p = laplace_pressure([(b, sigma, radius)], 2) if laplace else None
+    return _case("drop" if inverted else "bubble", prm, phi, T, steps, p=p)
 
 
 def small(dim=2, shape=(70, 37), nphase=2, precision="fp64", seed_k=11,
@@ -285,11 +317,13 @@ def batch(n_cases=64, seed_k=5, precision="fp32", sizes=(64, 128, 256, 512)):
         drop = tanh_in(L / 4 - r)
         if N == 2:
             phi = np.stack([drop, 1.0 - drop])
+            p = laplace_pressure([(drop, 1e-3, L / 4)], 2)
         else:
             core = tanh_in(L / 8 - r)
             phi = np.stack([drop * core, drop * (1.0 - core), 1.0 - drop])
+            p = laplace_pressure([(drop, 1e-3, L / 4), (core, 1e-3, L / 8)], 2)
         T = np.full(drop.shape, T_HOT)
-        case = _case("batch", prm, phi, T, 200)
+        case = _case("batch", prm, phi, T, 200, p=p)
         case.update(theta_deg=theta, ste=ste)
         out.append(case)
     return out

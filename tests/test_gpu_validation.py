@@ -165,28 +165,35 @@ def test_equal_tension_lens_has_120_degree_junctions():
 
 def test_impurities_workload_full_length_is_stable():
     """The 192^3 D3Q19 N = 4 impurities workload for its full 10 000 steps in
-    float32: no non-finite value, sum_p phi_p within 1e-2 of 1, the front
-    (volume-equivalent solid thickness) rising monotonically, and the masses
-    of the base liquid, the gas and the impurity droplet within 2e-3 of
-    their start at every 1000 steps.  (The small gas bubble breathes with the
-    pressure field through phi_p div u and is not held to a mass bar.)"""
+    float32, from the Young-Laplace pressure of its round interfaces: no
+    non-finite value, sum_p phi_p within 1e-2 of 1, the front
+    (volume-equivalent solid thickness) rising monotonically, and every
+    phase's mass near its start at every 1000 steps: the base liquid, the
+    gas and the impurity droplet within 2e-3, the small gas bubble within
+    BUBBLE_BAR (it follows the compression of the weakly compressible flow,
+    whose bulk modulus scales with the density)."""
     from paper_2603_22902_amd import Solver
     c = synth.impurities()
     s = Solver(c["params"])
     s.init_case(c)
     m0 = s.lbf_diagnostics()["mass"]
     front = 0.0
+    bars = np.array([2e-3, 2e-3, 2e-3, BUBBLE_BAR])
     for k in range(10):
         s.lbf_step(1000)
         d = s.lbf_diagnostics()
         drift = (d["mass"] - m0) / m0
-        print("step", 1000 * (k + 1), "front", d["front"], "drift", drift, flush=True)
+        print("step", 1000 * (k + 1), "front", d["front"], "drift", drift,
+              "sum_phi_err", d["max_sum_phi_err"], flush=True)
         assert not d["nonfinite"]
         assert d["max_sum_phi_err"] < 1e-2
         assert d["front"] > front
         front = d["front"]
-        assert np.all(np.abs(drift[:3]) < 2e-3), drift
+        assert np.all(np.abs(drift) < bars), drift
     assert front > 2.0
+
+
+BUBBLE_BAR = 5e-2
 
 
 @pytest.mark.parametrize("workload,nsteps,drift_bar,sumphi_bar", [
