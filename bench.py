@@ -8,15 +8,18 @@ workload: freezing with impurities, 192^3 D3Q19, N = 4, float32 storage
 memory, uploaded, and resident in HBM before timing starts.
 
 Prints one JSON line with MLUPS (million lattice updates per second, with
-conservation diagnostics every 100 steps inside the timed region), the
-HBM roofline of the dominant kernel, the collide pass (its algorithmic
-bytes per launch over its average launch time, measured with HIP events
-on the solver's stream around each launch), the same for the moments pass
-and for the whole step, and the FP64 CPU oracle timed on a bounded sample
-of the same workload.
+the conservation diagnostics inside the timed region: after every 100
+steps and after the last step), the HBM roofline of the step (the state's
+algorithmic bytes per step over the average durations of its two launches,
+the moments and the collide pass, measured with HIP events on the
+solver's stream around each launch), the same for each kernel, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--workload impurities|droplet|compound|film]
                   [--precision fp32|mixed|fp64] [--no-cpu-baseline]
+  python bench.py --probe MIB   only the library's float4 copy and read
+                                sweeps over MIB-MiB buffers (the known-size
+                                kernels that calibrate the HBM counters)
 """
 from __future__ import annotations
 
@@ -57,9 +60,10 @@ def algorithmic_bytes_per_cell(dim: int, N: int, elt: int) -> dict:
             "step": 2 * elt * ((N + 2) * Q + (N + dim + 3))}
 
 
-def measured_traffic(workload: str, precision: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources; else None."""
+def measured_traffic(workload: str, precision: str, kernel: str = "collide"):
+    """HBM bytes per launch (kernel="collide") or per step (kernel="step",
+    both launches) from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
@@ -67,7 +71,7 @@ def measured_traffic(workload: str, precision: str):
         rec = json.load(f)
     if rec.get("kernel_hash") != kernel_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch" if kernel == "collide" else "bytes_per_step")
 
 
 def traffic_rate(workload: str, precision: str, ms: float) -> float:
@@ -91,7 +95,7 @@ def describe(case) -> dict:
             "cells": int(p["nx"] * p["ny"] * (p["nz"] if p["dim"] == 3 else 1)),
             "nphase": p["nphase"], "lattice": f"D{p['dim']}Q{9 if p['dim'] == 2 else 19}",
             "storage": "f64" if p["precision"] == "fp64" else "f32",
-            "diag_interval": 100}
+            "diagnostics": "every 100 steps and after the last, inside the timed region"}
 
 
 def cpu_baseline(case, budget_s: float = 20.0) -> dict:
@@ -377,6 +381,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver's time step runs on one device; "
@@ -385,6 +390,15 @@ def main():
 
     import torch
     from paper_2603_22902_amd import Solver
+
+    if args.probe:
+        from paper_2603_22902_amd.lbfreeze import bandwidth_probe
+        bw = bandwidth_probe(0, mib=args.probe, reps=3)
+        print(json.dumps({"probe_mib": args.probe, "reps": 3,
+                          "bytes_per_copy_launch": 2 * (args.probe << 20),
+                          "bytes_per_read_launch": args.probe << 20,
+                          "copy_GB_s": round(bw["copy"] / 1e9, 1), "read_GB_s": round(bw["read"] / 1e9, 1)}))
+        return
 
     case = make_case(args.workload, args.precision)
     prm = case["params"]
@@ -399,7 +413,7 @@ def main():
     torch.cuda.synchronize()
     # per-phase mass and front position every 100 steps of the timed run
     # (the diagnostics are part of the timed work)
-    dlog = {"interval": 100, "step": [], "front": [], "mass_drift_max_rel": []}
+    dlog = {"interval": "every 100 steps and after the last", "step": [], "front": [], "mass_drift_max_rel": []}
 
     # Timed region 1 (the metric): K steps with diagnostics every 100 steps.
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -411,11 +425,10 @@ def main():
         n = min(100, args.steps - done)
         s.lbf_step(n)
         done += n
-        if n == 100:
-            d = s.lbf_diagnostics(check_nan=False)
-            dlog["step"].append(args.warmup + done)
-            dlog["front"].append(d["front"])
-            dlog["mass_drift_max_rel"].append(d["mass"])
+        d = s.lbf_diagnostics(check_nan=False)
+        dlog["step"].append(args.warmup + done)
+        dlog["front"].append(d["front"])
+        dlog["mass_drift_max_rel"].append(d["mass"])
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -462,6 +475,9 @@ def main():
     bpc = algorithmic_bytes_per_cell(prm["dim"], prm["nphase"], elt)
     achieved = bpc["collide"] * ncell / (ms_col * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, args.precision)
+    step_ms = ms_mom + ms_col
+    step_achieved = bpc["step"] * ncell / (step_ms * 1e-3) / 1e9
+    step_traffic = measured_traffic(args.workload, args.precision, kernel="step")
     ms_per_step = ms_total / args.steps
     mlups = ncell * args.steps / (ms_total * 1e-3) / 1e6
     dtype = {"fp32": "f32", "mixed": "f32 storage / f64 arithmetic", "fp64": "f64"}[args.precision]
@@ -475,10 +491,15 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic", "config": describe(case),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "collide_kernel", "kernel_us": round(ms_col * 1e3, 2),
-                     "bytes_per_cell": bpc["collide"]},
+        # The step (its two launches together) against the state's bytes:
+        # every population and lagged field read once and written once.
+        "roofline": {"bound": "hbm", "achieved": round(step_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(step_achieved / HBM_PEAK_GBS, 4), "traffic": step_traffic,
+                     "kernel": "step = moment_kernel + collide_kernel", "kernel_us": round(step_ms * 1e3, 2),
+                     "bytes_per_cell": bpc["step"],
+                     "dominant_kernel": {"kernel": "collide_kernel", "achieved": round(achieved, 1),
+                                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                                         "kernel_us": round(ms_col * 1e3, 2), "bytes_per_cell": bpc["collide"]}},
         "bandwidth_probe": probe,
         "host_io": host_io,
         "diagnostics": dlog,

@@ -259,7 +259,9 @@ lbf_status lbf_batch_bytes(lbf_ctx* const* ctxs, int n, size_t* bytes);
 lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t bytes, void* hip_stream,
                             lbf_batch** out);
 /* Row tile per phase count: tile[N-1] in {64, 128, 256}, 0 keeps the current
- * one (the default is 128). */
+ * one (the default is 128).  This and lbf_batch_tune rewrite the case tables
+ * and drop a captured graph: lbf_batch_replay then returns LBF_ESTATE until
+ * the next lbf_batch_capture. */
 lbf_status lbf_batch_set_tiles(lbf_batch* b, const int* tile);
 /* Autotuner: for each phase count, time trial_steps passes with each row tile
  * (passes that read the current states and write only the scratch buffers,

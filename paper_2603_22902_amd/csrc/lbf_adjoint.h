@@ -192,22 +192,25 @@ __host__ __device__ inline void adj_moment_cell(const AdjArgs<C>& a, const KPara
   using L = AdjLayout<C>;
   constexpr int Q = C::Q, NP = C::NP;
   const long long nc = P.ncell;
-  const R div = R(plane(a.ain, C::A_DIV, nc)[cell]);
-  const R qv = R(plane(a.ain, C::A_Q, nc)[cell]);
-  const R idiv = R(1) / (R(1) - R(0.5) * div);
+  // as the forward moments pass (compensated sums, float64 division)
+  const double div = double(plane(a.ain, C::A_DIV, nc)[cell]);
+  const double qv = double(plane(a.ain, C::A_Q, nc)[cell]);
+  const double idiv = 1.0 / (1.0 - 0.5 * div);
+  double phid[NP];
   R phi[NP];
   for (int p = 0; p < NP; ++p) {
-    R sum = R(0);
-    for (int i = 0; i < Q; ++i) sum += R(plane(a.pin, (1 + p) * Q + i, nc)[cell]);
-    phi[p] = sum * idiv;
+    MomSum<typename C::S> sum;
+    for (int i = 0; i < Q; ++i) sum.add(plane(a.pin, (1 + p) * Q + i, nc)[cell]);
+    phid[p] = double(typename C::S(sum.value() * idiv));
+    phi[p] = R(phid[p]);
   }
   double sh = 0.0;
   for (int i = 0; i < Q; ++i) sh += double(plane(a.pin, (NP + 1) * Q + i, nc)[cell]);
-  const double rhoH = sh + 0.5 * double(qv);
+  const double rhoH = sh + 0.5 * qv;
   double T, fl;
-  invert<NP>(P, phi, rhoH, T, fl);
+  invert<NP>(P, phid, rhoH, T, fl);
   for (int p = 0; p < NP; ++p) wplane(a, L::M_PHI + p, nc)[cell] = phi[p];
-  wplane(a, L::M_FS, nc)[cell] = R(1.0 - fl);
+  wplane(a, L::M_FS, nc)[cell] = R(typename C::S(1.0 - fl));
   wplane(a, L::M_RHOH, nc)[cell] = R(rhoH);
 }
 

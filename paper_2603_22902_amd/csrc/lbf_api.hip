@@ -122,11 +122,7 @@ void* aux_ptr(lbf_ctx* c, int k) { return c->base + c->lay.off_aux[k]; }
 double* stage_ptr(lbf_ctx* c) { return reinterpret_cast<double*>(c->base + c->lay.off_stage); }
 const lbf::KParams* kp_ptr(lbf_ctx* c) { return reinterpret_cast<const lbf::KParams*>(c->base + c->lay.off_kp); }
 
-bool all_finite(const double* a, long long n) {
-  for (long long k = 0; k < n; ++k)
-    if (!isfinite(a[k])) return false;
-  return true;
-}
+using lbf::all_finite;
 
 // Copy a device array of n stored values (the state's precision) to a
 // float64 host array, plane by plane through the staging buffer.
@@ -642,6 +638,8 @@ lbf_status lbf_adjoint_gradient(lbf_adj* a, double* grad) {
   HIPCHK(c, hipMemcpyAsync(grad, adj_acc(a), lbf::NPAR * sizeof(double), hipMemcpyDeviceToHost, a->stream),
          "hipMemcpyAsync");
   HIPCHK(c, hipStreamSynchronize(a->stream), "hipStreamSynchronize");
+  if (!all_finite(grad, lbf::NPAR))
+    return fail(c, LBF_ENAN, "non-finite gradient: the reverse sweep overflowed");
   return LBF_OK;
 }
 
@@ -744,10 +742,21 @@ void batch_table(const lbf_batch_group& g, int v, std::vector<lbf::BatchCase<S>>
   }
 }
 
+// A captured graph holds the launches of the case tables it was captured
+// with (tile variant, block counts); rewriting a table makes it stale, so it
+// is dropped and lbf_batch_replay refuses until the next lbf_batch_capture.
+void batch_drop_graph(lbf_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
 lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
   lbf_batch_group& g = b->g[gi];
   lbf_ctx* c0 = b->first;
   void* dst = b->base + g.off;
+  batch_drop_graph(b);
   if (c0->prm.precision == LBF_FP64) {
     std::vector<lbf::BatchCase<double>> t;
     batch_table<double>(g, v, t, g.cblocks, g.mblocks);
@@ -954,14 +963,7 @@ lbf_status lbf_batch_capture(lbf_batch* b) {
   if (!b) return LBF_EINVAL;
   lbf_ctx* c0 = b->first;
   ADJCHK(batch_check_members(b));
-  if (b->exec) {
-    (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
-  if (b->graph) {
-    (void)hipGraphDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  batch_drop_graph(b);
   HIPCHK(c0, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   lbf_status st = batch_launch(b, b->parity);
   if (st == LBF_OK) st = batch_launch(b, b->parity ^ 1);
@@ -993,8 +995,7 @@ lbf_status lbf_batch_replay(lbf_batch* b, int times) {
 
 lbf_status lbf_batch_destroy(lbf_batch* b) {
   if (!b) return LBF_OK;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  batch_drop_graph(b);
   delete b;
   return LBF_OK;
 }
@@ -1260,6 +1261,8 @@ lbf_status lbf_batch_adjoint_gradient(lbf_batch_adj* ba, double* grad) {
            "hipMemcpyAsync");
   }
   HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  if (!all_finite(grad, (long long)b->ncase * lbf::NPAR))
+    return fail(c0, LBF_ENAN, "non-finite gradient of some case: its reverse sweep overflowed");
   return LBF_OK;
 }
 

@@ -220,7 +220,8 @@ int run(const lbf_params* prm, const double* phi, const double* T, int nsteps, i
   a.lain = laA.data();
   for (int c = 0; c < (int)nc; ++c) adj_init_latent_cell<C>(a, P, c, gpar.data());
   for (int k = 0; k < NPAR; ++k) grad[k] = gpar[k];
-  return 0;
+  // as lbf_adjoint_gradient: a non-finite gradient is reported, not returned silently
+  return all_finite(grad, NPAR) && isfinite(*J) ? 0 : LBF_ENAN;
 }
 
 template <int DIM, typename S, typename R>

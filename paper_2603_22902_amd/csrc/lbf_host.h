@@ -13,6 +13,12 @@
 
 namespace lbf {
 
+inline bool all_finite(const double* a, long long n) {
+  for (long long k = 0; k < n; ++k)
+    if (!isfinite(a[k])) return false;
+  return true;
+}
+
 inline int lattice_q(int dim) { return dim == 2 ? 9 : 19; }
 
 // Validation of lbf_check_params; returns an empty string when valid.
@@ -157,7 +163,7 @@ inline Layout make_layout(const lbf_params* P) {
   L.off_stage = o;
   o = align256(o + (size_t)ncell * 8);
   L.off_part = o;
-  o = align256(o + (size_t)1024 * L.nv * 8);
+  o = align256(o + (size_t)DIAG_MAX_BLOCKS * L.nv * 8);
   L.off_out = o;
   o = align256(o + (size_t)L.nv * 8);
   L.off_kp = o;

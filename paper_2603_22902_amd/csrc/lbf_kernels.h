@@ -1,7 +1,6 @@
 // HIP kernels of the coupled LB solver and their launchers.
 //
-//   moment_kernel   phi_p^n, f_s^n of every cell (first pass of a step;
-//                   moment_kernel_v4: four cells per thread, float32 storage)
+//   moment_kernel   phi_p^n, f_s^n of every cell (first pass of a step)
 //   collide_kernel  finite differences, sources, collisions and push
 //                   streaming (or, with MOMENTS, one macroscopic field at
 //                   the current time level)
@@ -57,67 +56,6 @@ __global__ void __launch_bounds__(MOMENT_THREADS)
   a.aout = aout;
   const int cell = blockIdx.x * MOMENT_THREADS + threadIdx.x;
   if (cell < P.ncell) moment_cell<C>(a, P, cell);
-}
-
-// Moments pass over four consecutive cells per thread with 16-byte loads and
-// stores (float32 storage, cell count a multiple of 4): the wider loads
-// stream closer to the HBM read rate than one 4-byte load per plane and cell.
-// Each cell's arithmetic is that of moment_cell, in the same order, so the
-// result is bitwise the same.
-template <class C>
-__global__ void __launch_bounds__(MOMENT_THREADS)
-    moment_kernel_v4(const float* __restrict__ pin, const float* __restrict__ ain, float* __restrict__ aout,
-                     const KParams* __restrict__ kp) {
-  using R = typename C::R;
-  constexpr int Q = C::Q, NP = C::NP;
-  const KParams& P = *kp;
-  const long long nc = P.ncell;
-  const long long c0 = 4LL * ((long long)blockIdx.x * MOMENT_THREADS + threadIdx.x);
-  if (c0 >= nc) return;
-  const float4 dv = *reinterpret_cast<const float4*>(plane(ain, C::A_DIV, nc) + c0);
-  const float4 qv = *reinterpret_cast<const float4*>(plane(ain, C::A_Q, nc) + c0);
-  const float dva[4] = {dv.x, dv.y, dv.z, dv.w};
-  const float qva[4] = {qv.x, qv.y, qv.z, qv.w};
-  R idiv[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) idiv[k] = R(1) / (R(1) - R(0.5) * R(dva[k]));
-  R phi[4][NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    R sum[4] = {R(0), R(0), R(0), R(0)};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const float4 v = *reinterpret_cast<const float4*>(plane(pin, (1 + p) * Q + i, nc) + c0);
-      sum[0] += R(v.x);
-      sum[1] += R(v.y);
-      sum[2] += R(v.z);
-      sum[3] += R(v.w);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) phi[k][p] = sum[k] * idiv[k];
-  }
-  double sh[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float4 v = *reinterpret_cast<const float4*>(plane(pin, (NP + 1) * Q + i, nc) + c0);
-    sh[0] += double(v.x);
-    sh[1] += double(v.y);
-    sh[2] += double(v.z);
-    sh[3] += double(v.w);
-  }
-  float fsv[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double rhoH = sh[k] + 0.5 * double(R(qva[k]));
-    double T, fl;
-    invert<NP>(P, phi[k], rhoH, T, fl);
-    fsv[k] = float(R(1.0 - fl));
-  }
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-    *reinterpret_cast<float4*>(plane(aout, p, nc) + c0) =
-        make_float4(float(phi[0][p]), float(phi[1][p]), float(phi[2][p]), float(phi[3][p]));
-  *reinterpret_cast<float4*>(plane(aout, C::A_FS, nc) + c0) = make_float4(fsv[0], fsv[1], fsv[2], fsv[3]);
 }
 
 // The buffers are separate kernel parameters so that the compiler knows
@@ -246,24 +184,25 @@ __host__ __device__ inline void diag_cell(const KParams& P, const S* pop, const 
                                           long long cell, double* acc) {
   constexpr int Q = Lat<DIM>::Q;
   const long long nc = P.ncell;
-  const R div = R(aux[(NP + 1 + DIM) * nc + cell]);
-  const R qv = R(aux[(NP + 2 + DIM) * nc + cell]);
-  R phi[NP];
+  // phi_p and f_s exactly as the moments pass forms and stores them
+  const double idiv = 1.0 / (1.0 - 0.5 * double(aux[(NP + 1 + DIM) * nc + cell]));
+  const double qv = double(aux[(NP + 2 + DIM) * nc + cell]);
+  double phi[NP];
   for (int p = 0; p < NP; ++p) {
-    R sum = R(0);
-    for (int i = 0; i < Q; ++i) sum += R(pop[((1 + p) * Q + i) * nc + cell]);
-    phi[p] = sum / (R(1) - R(0.5) * div);
+    MomSum<S> sum;
+    for (int i = 0; i < Q; ++i) sum.add(pop[((1 + p) * Q + i) * nc + cell]);
+    phi[p] = double(S(sum.value() * idiv));
   }
   double sh = 0.0;
   for (int i = 0; i < Q; ++i) sh += double(pop[((NP + 1) * Q + i) * nc + cell]);
-  const double rhoH = sh + 0.5 * double(qv);
+  const double rhoH = sh + 0.5 * qv;
   double T, fl;
   invert<NP>(P, phi, rhoH, T, fl);
-  const double fs = double(R(1.0 - fl));
+  const double fs = double(S(1.0 - fl));
   double s = 0.0, psi = 0.0;
   bool bad = !(rhoH == rhoH) || rhoH - rhoH != 0.0;
   for (int p = 0; p < NP; ++p) {
-    const double ph = double(phi[p]);
+    const double ph = phi[p];
     acc[p] += ph * (fs * P.rho_s[p] + (1.0 - fs) * P.rho_l[p]);
     acc[NP + p] += fs * ph;
     acc[2 * NP + p] += ph;
@@ -279,6 +218,42 @@ __host__ __device__ inline void diag_cell(const KParams& P, const S* pop, const 
 }
 
 constexpr int DIAG_THREADS = 256;
+constexpr int DIAG_WAVES = DIAG_THREADS / 64;
+
+// Combine of two partial diagnostics: maxima (with NaN kept) for the
+// largest |sum phi - 1| and the non-finite flag, sums for the rest.
+template <int NP>
+__device__ inline double diag_combine(int k, double a, double b) {
+  if (k == 3 * NP + 1 || k == 3 * NP + 3) return (a > b || !(a == a)) ? a : b;
+  return a + b;
+}
+
+// Block reduction of NV values per thread: a butterfly over the 64 lanes of
+// each wavefront (cross-lane shuffles, no barrier), then one value per wave
+// through LDS, combined by the first wave in wave order.  The order of the
+// combines is fixed, so the result is deterministic.  Thread 0 returns the
+// block's values in v.
+template <int NP>
+__device__ inline void diag_block_reduce(double* v, double (*red)[DIAG_WAVES]) {
+  constexpr int NV = DiagN<NP>::NV;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] = diag_combine<NP>(k, v[k], __shfl_xor(v[k], off, 64));
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = red[k][0];
+#pragma unroll
+      for (int w = 1; w < DIAG_WAVES; ++w) a = diag_combine<NP>(k, a, red[k][w]);
+      v[k] = a;
+    }
+}
 
 template <int DIM, int NP, typename S, typename R>
 __global__ void __launch_bounds__(DIAG_THREADS)
@@ -286,62 +261,32 @@ __global__ void __launch_bounds__(DIAG_THREADS)
                 double* __restrict__ part) {
   const KParams& P = *kp;
   constexpr int NV = DiagN<NP>::NV;
-  __shared__ double red[NV][DIAG_THREADS];
+  __shared__ double red[NV][DIAG_WAVES];
   double acc[NV];
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < P.ncell; c += stride)
     diag_cell<DIM, NP, S, R>(P, pop, aux, c, acc);
-  for (int k = 0; k < NV; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      for (int k = 0; k < NV; ++k) {
-        const double a = red[k][threadIdx.x], b = red[k][threadIdx.x + s];
-        if (k == 3 * NP + 1 || k == 3 * NP + 3)
-          red[k][threadIdx.x] = (a > b || !(a == a)) ? a : b;
-        else
-          red[k][threadIdx.x] = a + b;
-      }
-    }
-    __syncthreads();
-  }
+  diag_block_reduce<NP>(acc, red);
   if (threadIdx.x == 0)
-    for (int k = 0; k < NV; ++k) part[(long long)blockIdx.x * NV + k] = red[k][0];
+    for (int k = 0; k < NV; ++k) part[(long long)blockIdx.x * NV + k] = acc[k];
 }
 
 template <int NP>
 __global__ void __launch_bounds__(DIAG_THREADS) diag_final_kernel(const double* part, int nparts,
                                                                   double inv_area, double* out) {
   constexpr int NV = DiagN<NP>::NV;
-  __shared__ double red[NV][DIAG_THREADS];
+  __shared__ double red[NV][DIAG_WAVES];
+  double acc[NV];
   for (int k = 0; k < NV; ++k) {
     double a = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += DIAG_THREADS) {
-      const double v = part[(long long)b * NV + k];
-      if (k == 3 * NP + 1 || k == 3 * NP + 3)
-        a = (v > a || !(v == v)) ? v : a;
-      else
-        a += v;
-    }
-    red[k][threadIdx.x] = a;
+    for (int b = threadIdx.x; b < nparts; b += DIAG_THREADS) a = diag_combine<NP>(k, a, part[(long long)b * NV + k]);
+    acc[k] = a;
   }
-  __syncthreads();
-  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      for (int k = 0; k < NV; ++k) {
-        const double a = red[k][threadIdx.x], b = red[k][threadIdx.x + s];
-        if (k == 3 * NP + 1 || k == 3 * NP + 3)
-          red[k][threadIdx.x] = (a > b || !(a == a)) ? a : b;
-        else
-          red[k][threadIdx.x] = a + b;
-      }
-    }
-    __syncthreads();
-  }
+  diag_block_reduce<NP>(acc, red);
   if (threadIdx.x == 0) {
-    for (int k = 0; k < NV; ++k) out[k] = red[k][0];
-    out[3 * NP + 2] = red[3 * NP + 2][0] * inv_area;
+    for (int k = 0; k < NV; ++k) out[k] = acc[k];
+    out[3 * NP + 2] = acc[3 * NP + 2] * inv_area;
   }
 }
 
@@ -394,23 +339,12 @@ inline hipError_t launch_step(StepArgs<S> a, const KParams& hostP, const KParams
   a.nblocks = g.nblocks;
   a.mom = a.aout;
   const int mb = (int)((hostP.ncell + MOMENT_THREADS - 1) / MOMENT_THREADS);
-  if (passes & 1) {
-    // float4 path: float32 storage, whole quads of cells, 16-byte aligned
-    // planes (caller-supplied device states need not be)
-    bool v4 = false;
-    if constexpr (sizeof(S) == 4)
-      v4 = hostP.ncell % 4 == 0 && ((reinterpret_cast<uintptr_t>(a.pin) | reinterpret_cast<uintptr_t>(a.ain) |
-                                     reinterpret_cast<uintptr_t>(a.aout)) & 15) == 0;
-    if (v4) {
-      const int mb4 = (int)((hostP.ncell / 4 + MOMENT_THREADS - 1) / MOMENT_THREADS);
-      hipLaunchKernelGGL((moment_kernel_v4<C>), dim3(mb4), dim3(MOMENT_THREADS), 0, s,
-                         reinterpret_cast<const float*>(a.pin), reinterpret_cast<const float*>(a.ain),
-                         reinterpret_cast<float*>(a.aout), dP);
-    } else {
-      hipLaunchKernelGGL((moment_kernel<C>), dim3(mb), dim3(MOMENT_THREADS), 0, s, a.pin, a.ain, a.aout,
-                         a, dP);
-    }
-  }
+  // One cell per thread (57 VGPRs, eight waves per SIMD): the compensated
+  // float32 sums of the moments hide their latency behind many waves.  A
+  // four-cells-per-thread variant with 16-byte loads ran at one wave per
+  // SIMD and took 670 us against 552 us on the 192^3 workload.
+  if (passes & 1)
+    hipLaunchKernelGGL((moment_kernel<C>), dim3(mb), dim3(MOMENT_THREADS), 0, s, a.pin, a.ain, a.aout, a, dP);
   if (!(passes & 2)) return hipGetLastError();
   if (moments)
     hipLaunchKernelGGL((collide_kernel<C, true>), dim3(g.nblocks), dim3(g.threads), 0, s, a.pin,
@@ -436,12 +370,12 @@ inline hipError_t launch_init(const KParams& P, const KParams* dP, const double*
   return hipGetLastError();
 }
 
-constexpr int DIAG_BLOCKS = 1024;
+static_assert(DIAG_THREADS == 256, "diag_blocks assumes 256-thread blocks");
 
 template <int DIM, int NP, typename S, typename R>
 inline hipError_t launch_diag(const KParams& P, const KParams* dP, const S* pop, const S* aux,
                               double* part, double* out, hipStream_t s) {
-  const int nb = grid_for(P.ncell, DIAG_THREADS, DIAG_BLOCKS);
+  const int nb = diag_blocks(P.ncell);
   hipLaunchKernelGGL((diag_kernel<DIM, NP, S, R>), dim3(nb), dim3(DIAG_THREADS), 0, s, dP, pop, aux,
                      part);
   hipLaunchKernelGGL((diag_final_kernel<NP>), dim3(1), dim3(DIAG_THREADS), 0, s, part, nb,

@@ -16,6 +16,14 @@ namespace lbf {
 
 constexpr int MAXP = 4;
 
+// Blocks of the first diagnostics pass (256 threads each, grid-strided,
+// at most DIAG_MAX_BLOCKS): each writes one row of per-block partials.
+constexpr int DIAG_MAX_BLOCKS = 1024;
+inline int diag_blocks(long long ncell) {
+  const long long b = (ncell + 255) / 256;
+  return b > DIAG_MAX_BLOCKS ? DIAG_MAX_BLOCKS : (b < 1 ? 1 : (int)b);
+}
+
 template <int DIM>
 struct Lat;
 

@@ -76,5 +76,14 @@ def adjoint(params, phi, T, nsteps, objective="frozen_fraction"):
     rc = _lib().lbf_emu_adjoint(ctypes.byref(P), _p(phi), _p(T), int(nsteps),
                                  OBJECTIVES[objective], _p(J), _p(g))
     if rc != 0:
-        raise RuntimeError(f"lbf_emu_adjoint failed ({rc})")
+        raise EmulatorError(rc, float(J[0]), g)
     return float(J[0]), g
+
+
+class EmulatorError(RuntimeError):
+    """A non-zero status of the emulated reverse sweep (LBF_ENAN = -5 for a
+    non-finite objective or gradient); J and grad hold what was computed."""
+
+    def __init__(self, rc, J, grad):
+        super().__init__(f"lbf_emu_adjoint failed ({rc})")
+        self.rc, self.J, self.grad = rc, J, grad

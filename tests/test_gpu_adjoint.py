@@ -41,6 +41,40 @@ def test_gpu_adjoint_matches_oracle_gradient():
         assert abs(pick(g["raw"]) - fd) <= 1e-4 * abs(fd) + 1e-10, (key, idx, pick(g["raw"]), fd)
 
 
+@pytest.mark.parametrize("N", [2, 3])
+def test_gpu_adjoint_matches_oracle_gradient_multi_tile(N):
+    """300 x 40 (two full 128-cell row tiles and a ragged third, several
+    wall-normal chunks of the tiled passes), float64, 12 steps: the GPU
+    reverse sweep against central differences of the FP64 oracle within
+    1e-4."""
+    spec = (N, ("wall", "open"), ("dirichlet", "dirichlet"), 70.0)
+    case = make_case(*spec, shape=(300, 40))
+    prm = case["params"]
+    n = 12
+    print("multi-tile adjoint", spec, flush=True)
+    J, g = _grad(case, n, 5)
+    assert abs(J - oracle_J(case, prm, n)) <= 1e-12
+    fj = lambda q: oracle_J(case, q, n)
+    scale = np.abs(g["raw"]).max()
+    for key, idx, h, pick in checks(prm):
+        fd = central(fj, prm, key, idx, 10 * h)
+        assert abs(pick(g["raw"]) - fd) <= 1e-4 * abs(fd) + 1e-8 * scale, (key, idx, pick(g["raw"]), fd)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_gpu_adjoint_matches_emulator_across_tiles(N):
+    """261 x 12 (the tiled collide reverse and gather across two tile
+    boundaries and the periodic wrap): the GPU sweep against the host
+    emulator of the same passes, float64, within 1e-10 of the gradient's
+    scale."""
+    spec = (N, ("wall", "open"), ("dirichlet", "dirichlet"), 70.0)
+    case = make_case(*spec, shape=(261, 12))
+    J, g = _grad(case, 10, 10)
+    Je, ge = emulator.adjoint(case["params"], case["phi"], case["T"], 10)
+    assert abs(J - Je) <= 1e-13
+    assert np.abs(g["raw"] - ge).max() <= 1e-10 * np.abs(ge).max(), (g["raw"], ge)
+
+
 def test_gpu_front_gradient_matches_emulator_and_oracle():
     """The front-position objective (sum f_s psi per wall-layer cell): the
     float64 sweep against the emulator, and against central differences of

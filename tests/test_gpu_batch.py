@@ -63,6 +63,59 @@ def test_graph_replays_equal_eager_steps():
             assert np.array_equal(s.lbf_get_populations(), r.lbf_get_populations()), k
 
 
+def test_changing_tiles_after_capture_drops_the_graph():
+    """lbf_batch_set_tiles rewrites the case tables a captured graph was
+    built from: replay is refused (LBF_ESTATE) until the next capture, and
+    the re-captured graph again equals the eager steps."""
+    from paper_2603_22902_amd.batch import Batch
+    from paper_2603_22902_amd.lbfreeze import LbfError, LBF_ESTATE
+    cases = _cases()
+    ref = _solvers(cases)
+    got = _solvers(cases)
+    b = Batch(got)
+    b.set_tiles({2: 128, 3: 128})
+    b.capture()
+    b.set_tiles({2: 64, 3: 256})
+    with pytest.raises(LbfError) as e:
+        b.replay(1)
+    assert e.value.status == LBF_ESTATE
+    b.capture()
+    b.replay(2)
+    b.synchronize()
+    for s in ref:
+        s.lbf_step(4)
+    for s, r in zip(got, ref):
+        assert s.step_count() == 4
+        assert np.array_equal(s.lbf_get_populations(), r.lbf_get_populations())
+
+
+def test_batch_matches_the_oracle_elementwise():
+    """Each case of a ragged batch (N = 1 to 4, sides 37 x 11 to 520 x 24,
+    one case wider than four 128-cell row tiles, walls and open faces),
+    stepped as one batch, against the FP64 oracle run of the same case:
+    every moment within 1e-12 (float64) after 20 steps."""
+    import oracle
+    from paper_2603_22902_amd.batch import Batch
+    from parity_util import compare_moments
+    specs = [((37, 11), 1, ("wall", "wall")), ((520, 24), 2, ("wall", "open")),
+             ((131, 29), 3, ("wall", "wall")), ((261, 17), 4, ("wall", "open")),
+             ((64, 64), 2, ("wall", "wall"))]
+    cases = [synth.stress(synth.small(dim=2, shape=sh, nphase=N, precision="fp64", flow_bc=fb,
+                                      therm_bc=("dirichlet", "adiabatic"), theta_deg=70.0))
+             for sh, N, fb in specs]
+    got = _solvers(cases)
+    b = Batch(got)
+    b.step(20)
+    b.synchronize()
+    for c, s in zip(cases, got):
+        o = oracle.Oracle(c["params"])
+        o.init_case(c)
+        o.step(20)
+        errs, bad = compare_moments(s.lbf_get_moments(), o.moments(), "fp64", c["params"])
+        print("batch case", c["T"].shape, c["params"]["nphase"], {k: f"{v:.1e}" for k, v in errs.items()})
+        assert not bad, (c["T"].shape, errs)
+
+
 def test_autotune_keeps_the_states():
     from paper_2603_22902_amd.batch import Batch
     cases = _cases()

@@ -65,15 +65,7 @@ def test_parity_small_stress(spec):
     print(f"parity case {spec}", flush=True)
     s, o = _run_pair(case, 30)
     errs, bad = compare_moments(s.lbf_get_moments(), o.moments(), prec, case["params"])
-    if prec == "fp32" and N == 1:
-        # One freezing phase everywhere, every cell near T_melt: rho H is
-        # mostly latent heat (~10) against T <= 0.7, so T = (rho H - latent
-        # part) / (rho C) carries ~14x the float32 rounding of rho H, and
-        # mdot follows T.  The host emulator of the same float32 arithmetic
-        # shows the same T and mdot errors against the oracle (2.6e-5,
-        # 3.2e-5), and float32 storage with float64 arithmetic ("mixed")
-        # meets 2e-5 on the same case.  Bar for those two fields: 1e-4.
-        bad = {k: v for k, v in bad.items() if not (k in ("T", "mdot") and v <= 1e-4)}
+    print("errors", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     assert not bad, errs
     assert rel_err(s.lbf_get_populations(), o.populations(), prec) <= TOL[prec]
     assert rel_err(s.lbf_get_aux(), o.aux(), prec) <= TOL[prec]
@@ -123,20 +115,31 @@ def test_parity_droplet_256_mixed():
 
 
 def test_parity_droplet_256_fp32_arithmetic():
-    """The same in float32 arithmetic.  Conserved fields and psi f_l keep the
-    2e-5 bar; u, p and T lose precision on the gas side of the 1000:1
-    interface, where float32 rounding of the force and momentum is divided
-    by the gas density (and T = rho H / (rho C) there), and are held to 5e-4
-    (measured 1.4e-4)."""
+    """The same in float32 arithmetic.  Every field but u and p keeps the
+    2e-5 bar.  u and p are held to 2e-4 (measured 1.2e-4 and 2.0e-5): their
+    error is float32 arithmetic at the freezing contact line, where the gas
+    velocity spikes between steps 50 and 100 (the error is 2.2e-6 at step
+    50); the whole collide pass in float64 still gives 4e-5, and the
+    mixed-precision test above meets 2e-5 on the same case."""
     case = synth.droplet(precision="fp32")
     s, o = _run_pair(case, 100)
     got, ref = s.lbf_get_moments(), o.moments()
-    errs, bad = compare_moments(got, ref, "fp32", case["params"], fields=("phi", "rhoH", "fl", "rho", "mdot"))
+    errs, bad = compare_moments(got, ref, "fp32", case["params"], fields=("phi", "rhoH", "T", "fl", "rho", "mdot"))
     print("droplet fp32", errs)
     assert not bad, errs
-    errs2, bad2 = compare_moments(got, ref, "fp32", case["params"], fields=("T", "u", "p"), tol=5e-4)
+    errs2, bad2 = compare_moments(got, ref, "fp32", case["params"], fields=("u", "p"), tol=2e-4)
     print("droplet fp32 flow", errs2)
     assert not bad2, errs2
+
+
+def test_parity_compound_512_fp32():
+    """The compound droplet (512^2, N = 3) in float32, the precision of the
+    adjoint's benchmark run: every field within 2e-5 after 40 steps."""
+    case = synth.compound(precision="fp32")
+    s, o = _run_pair(case, 40)
+    errs, bad = compare_moments(s.lbf_get_moments(), o.moments(), "fp32", case["params"])
+    print("compound fp32", errs)
+    assert not bad, errs
 
 
 def test_parity_compound_512_mixed():
@@ -238,33 +241,3 @@ def test_bandwidth_probe_rates_are_plausible():
     assert L.lbf_bandwidth_probe(p, p, 1 << 19, None, 1, lbfreeze._ptr(c), lbfreeze._ptr(r)) == lbfreeze.LBF_EINVAL
     assert L.lbf_bandwidth_probe(ctypes.c_void_p(a.data_ptr() + 4), ctypes.c_void_p(a.data_ptr() + (1 << 19)),
                                  1 << 18, None, 1, lbfreeze._ptr(c), lbfreeze._ptr(r)) == lbfreeze.LBF_EINVAL
-
-
-@pytest.mark.parametrize("dim,shape,N", [(3, (24, 20, 16), 4), (2, (96, 40), 3)])
-def test_moments_float4_path_bitwise_equals_per_cell_path(dim, shape, N):
-    """The four-cells-per-thread moments pass (16-byte aligned float32
-    planes) and the one-cell-per-thread pass (taken for planes that are not
-    16-byte aligned) give bitwise the same step."""
-    import torch
-
-    from paper_2603_22902_amd import Solver
-    case = synth.stress(synth.small(dim=dim, shape=shape, nphase=N, precision="fp32"), phi_noise=1e-4)
-    s = Solver(case["params"])
-    s.init_case(case)
-    s.lbf_step(3)
-    nb = s.state_device_bytes()
-    assert s.ncell % 4 == 0
-    buf = torch.empty(4 * nb + 1024, dtype=torch.uint8, device=s.device)
-    base = (256 - buf.data_ptr() % 256) % 256
-    al = [buf[base + k * nb: base + (k + 1) * nb] for k in range(2)]       # 16-byte aligned
-    mis = [buf[base + 2 * nb + 4 + k * nb: base + 2 * nb + 4 + (k + 1) * nb] for k in range(2)]  # 4 off
-    assert al[0].data_ptr() % 16 == 0 and mis[0].data_ptr() % 16 == 4
-    s.lbf_state_to_device(al[0])
-    s.lbf_state_to_device(mis[0])
-    for _ in range(2):
-        s.lbf_step_states(al[0], al[1])
-        s.lbf_step_states(mis[0], mis[1])
-        al.reverse()
-        mis.reverse()
-    torch.cuda.synchronize()
-    assert torch.equal(al[0], mis[0])

@@ -60,7 +60,8 @@ def test_table1_full_freeze_sweep():
         print(f"rho_s/rho_l {ratio:.2f} Ste {ste:.2f}: h_f/h_0 {hf:.4f} analytic {analytic:.4f} "
               f"error {err:.2e} mass drift {d['mass'][0] / m0 - 1:.2e} frozen {fz}")
         assert fz, (ratio, ste)
-        assert err < 0.05, (ratio, ste, hf, analytic)
+        # measured worst 1.6e-3; the paper's own numbers deviate by up to 2.4e-2
+        assert err < 5e-3, (ratio, ste, hf, analytic)
         # the lagged divergence (reading R2) conserves sum phi exactly only
         # at u = 0; over ~1e5 steps of expansion flow the phase mass drifts
         # by O(1e-3) (measured 1.6e-3 at rho_s/rho_l = 0.7)
@@ -124,7 +125,8 @@ def test_table2_janus_wetting_lengths():
         e1, e2 = abs(g1 - L1) / L1, abs(g2 - L2) / L2
         print(f"theta_23 {th23:.0f}: L1 {g1:.4f} (analytic {L1:.4f}, {e1:.2e})  "
               f"L2 {g2:.4f} (analytic {L2:.4f}, {e2:.2e})")
-        assert e1 < 0.05 and e2 < 0.05, (th23, g1, g2)
+        # measured worst 1.3e-2 (L_2 at 30 deg); the paper's own errors reach 3e-2
+        assert e1 < 3e-2 and e2 < 3e-2, (th23, g1, g2)
 
 
 def test_equal_tension_lens_has_120_degree_junctions():
@@ -160,7 +162,8 @@ def test_equal_tension_lens_has_120_degree_junctions():
 
     ratio, width = _relax(b, [s], shape, tol=5e-4)[0]
     print(f"lens thickness/width {ratio:.4f} (tan 30 = {math.tan(math.radians(30)):.4f}), width {width:.1f}")
-    assert abs(ratio - math.tan(math.radians(30.0))) < 0.1 * math.tan(math.radians(30.0))
+    # measured 0.5758 against 0.5774 (0.3 %)
+    assert abs(ratio - math.tan(math.radians(30.0))) < 0.02 * math.tan(math.radians(30.0))
 
 
 def test_impurities_workload_full_length_is_stable():
@@ -193,7 +196,8 @@ def test_impurities_workload_full_length_is_stable():
     assert front > 2.0
 
 
-BUBBLE_BAR = 5e-2
+# measured: the bubble breathes between -0.3 % and +4.4 % of its start over the run
+BUBBLE_BAR = 6e-2
 
 
 @pytest.mark.parametrize("workload,nsteps,drift_bar,sumphi_bar", [
