@@ -166,6 +166,19 @@ lbf_status lbf_get_aux(lbf_ctx* ctx, double* out);
  * Returns LBF_ENAN (sticky until lbf_init_fields/lbf_load_state) if so. */
 lbf_status lbf_diagnostics(lbf_ctx* ctx, double* out);
 
+/* lbf_diagnostics for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops): the same values and
+ * status, with the reduction's per-block partials and result kept in a
+ * static device array of LBF_DIAG_MAX_BLOCKS * LBF_DIAG_MAX_VALUES +
+ * LBF_DIAG_MAX_VALUES doubles (131 KB, one copy per device, held until the
+ * process ends) instead of the context's buffer.  Calls no allocating
+ * routine.  Calls that overlap on one device share that array and race:
+ * serialise them (one stream, or host synchronisation).  LBF_EINVAL if the
+ * reduction would need more than the array holds (never for N <= 4). */
+#define LBF_DIAG_MAX_BLOCKS 1024
+#define LBF_DIAG_MAX_VALUES 16
+lbf_status lbf_diagnostics_noalloc(lbf_ctx* ctx, double* out);
+
 /* Opaque snapshot of the whole state (populations, lagged fields, step
  * count).  bytes must equal lbf_snapshot_bytes. */
 lbf_status lbf_snapshot_bytes(const lbf_ctx* ctx, size_t* bytes);

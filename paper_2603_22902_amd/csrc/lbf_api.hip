@@ -390,6 +390,55 @@ lbf_status lbf_diagnostics(lbf_ctx* c, double* out) {
   return LBF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// lbf_diagnostics_noalloc: the same reduction with its per-block partials and
+// its result in a file-scope device array instead of the context's buffer.
+// Each device holds its own copy of the array; its address is looked up once
+// per device (with that device current) and kept, because the array's name
+// in host code is not a device address.  Calls that overlap on one device
+// share the array and race; every value the kernels read is written earlier
+// in the same call, so nothing needs clearing.
+// ---------------------------------------------------------------------------
+namespace {
+static_assert(LBF_DIAG_MAX_BLOCKS == lbf::DIAG_MAX_BLOCKS, "scratch rows = diagnostics blocks");
+static_assert(LBF_DIAG_MAX_VALUES >= 3 * lbf::MAXP + 4, "scratch row holds every diagnostic value");
+constexpr int kDiagScratchDoubles = LBF_DIAG_MAX_BLOCKS * LBF_DIAG_MAX_VALUES + LBF_DIAG_MAX_VALUES;
+static __device__ __align__(256) double scratch[kDiagScratchDoubles];
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices];  // per device, NULL until looked up
+}  // namespace
+
+lbf_status lbf_diagnostics_noalloc(lbf_ctx* c, double* out) {
+  if (!c) return LBF_EINVAL;
+  if (!out) return fail(c, LBF_EINVAL, "out is NULL");
+  if (!c->initialized) return fail(c, LBF_ESTATE, "lbf_init_fields has not been called");
+  if (c->device < 0 || c->device >= kMaxDevices)
+    return fail(c, LBF_ENOTSUP, "device index beyond the static scratch table");
+  const int nblocks = lbf::diag_blocks(c->ncell);
+  if (nblocks > LBF_DIAG_MAX_BLOCKS || c->lay.nv > LBF_DIAG_MAX_VALUES)
+    return fail(c, LBF_EINVAL, "diagnostic partials exceed the static scratch array");
+  if (!g_scratch_ptr[c->device]) {
+    int prev = -1;
+    HIPCHK(c, hipGetDevice(&prev), "hipGetDevice");
+    HIPCHK(c, hipSetDevice(c->device), "hipSetDevice");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    HIPCHK(c, hipSetDevice(prev), "hipSetDevice");
+    HIPCHK(c, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[c->device] = static_cast<double*>(ptr);
+  }
+  double* part = g_scratch_ptr[c->device];
+  double* dout = part + (size_t)LBF_DIAG_MAX_BLOCKS * LBF_DIAG_MAX_VALUES;
+  HIPCHK(c, c->ops->diag(c->kp, kp_ptr(c), pop_ptr(c, c->cur), aux_ptr(c, c->cur), part, dout, c->stream),
+         "diag kernel");
+  HIPCHK(c, hipMemcpyAsync(out, dout, (size_t)c->lay.nv * 8, hipMemcpyDeviceToHost, c->stream),
+         "hipMemcpyAsync");
+  HIPCHK(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (out[3 * c->N + 3] != 0.0) c->nan_flag = true;
+  if (c->nan_flag) return fail(c, LBF_ENAN, "non-finite order parameter or enthalpy in the state");
+  return LBF_OK;
+}
+
 lbf_status lbf_snapshot_bytes(const lbf_ctx* c, size_t* bytes) {
   if (!c || !bytes) return LBF_EINVAL;
   *bytes = sizeof(SnapHeader) + c->lay.pop_bytes + c->lay.aux_bytes;

@@ -101,6 +101,7 @@ def lib():
         L.lbf_get_populations.argtypes = [vp, _PD]
         L.lbf_get_aux.argtypes = [vp, _PD]
         L.lbf_diagnostics.argtypes = [vp, _PD]
+        L.lbf_diagnostics_noalloc.argtypes = [vp, _PD]
         L.lbf_snapshot_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_save_state.argtypes = [vp, vp, ctypes.c_size_t]
         L.lbf_load_state.argtypes = [vp, vp, ctypes.c_size_t]
@@ -112,7 +113,7 @@ def lib():
         L.lbf_status_string.argtypes = [ctypes.c_int]
         for name in ("lbf_check_params", "lbf_state_bytes", "lbf_create", "lbf_init_fields",
                      "lbf_step", "lbf_step_timed", "lbf_get_moments", "lbf_get_populations", "lbf_get_aux",
-                     "lbf_diagnostics", "lbf_snapshot_bytes", "lbf_save_state", "lbf_load_state",
+                     "lbf_diagnostics", "lbf_diagnostics_noalloc", "lbf_snapshot_bytes", "lbf_save_state", "lbf_load_state",
                      "lbf_step_count", "lbf_destroy", "lbf_state_device_bytes",
                      "lbf_state_to_device", "lbf_state_from_device", "lbf_step_states", "lbf_adjoint_bytes",
                      "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_seed_objective", "lbf_adjoint_step", "lbf_adjoint_finish",
@@ -284,10 +285,13 @@ class Solver:
         self._check(lib().lbf_get_aux(self._h, _ptr(out)))
         return out
 
-    def lbf_diagnostics(self, check_nan: bool = True) -> dict:
+    def lbf_diagnostics(self, check_nan: bool = True, noalloc: bool = False) -> dict:
+        """lbf_diagnostics, or with noalloc=True lbf_diagnostics_noalloc (the
+        same values from the library's static device scratch array)."""
         N = self.N
         out = np.empty(3 * N + 4)
-        s = lib().lbf_diagnostics(self._h, _ptr(out))
+        fn = lib().lbf_diagnostics_noalloc if noalloc else lib().lbf_diagnostics
+        s = fn(self._h, _ptr(out))
         if s != LBF_ENAN or check_nan:
             self._check(s)
         return dict(mass=out[:N].copy(), vol_solid=out[N:2 * N].copy(), vol=out[2 * N:3 * N].copy(),
