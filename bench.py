@@ -60,6 +60,26 @@ def algorithmic_bytes_per_cell(dim: int, N: int, elt: int) -> dict:
             "step": 2 * elt * ((N + 2) * Q + (N + dim + 3))}
 
 
+def algorithmic_bytes_reverse(dim: int, N: int, elt: int) -> dict:
+    """Bytes per cell the two reverse-step passes must move at least (2D
+    tiled passes; every value read once and written once).
+
+    collide reverse: reads the populations of x^n and their adjoints
+        (2 (N+2) Q), phi_p and f_s of x^n (N+1), the lagged fields it uses
+        (N + dim + 2), the per-cell adjoint scalars (N+1) and the adjoints of
+        u, D, q (dim + 2); writes the population adjoints ((N+2) Q) and its
+        work planes (finite-difference, own-cell and lagged adjoints, rho H:
+        2 N dim + 3 N + 2 dim + 5).
+    gather: reads those work planes and the moments it reverses
+        (2 N dim + 6 N + 2 dim + 8); writes the adjoint scalars and lagged
+        fields (2 N + dim + 4).
+    """
+    Q = 9 if dim == 2 else 19
+    col = elt * ((2 * (N + 2) * Q + 3 * N + 2 * dim + 6) + ((N + 2) * Q + 2 * N * dim + 3 * N + 2 * dim + 5))
+    gat = elt * ((2 * N * dim + 6 * N + 2 * dim + 8) + (2 * N + dim + 4))
+    return {"collide_reverse": col, "gather": gat, "reverse_step": col + gat}
+
+
 def measured_traffic(workload: str, precision: str, kernel: str = "collide"):
     """HBM bytes per launch (kernel="collide") or per step (kernel="step",
     both launches) from the committed rocprofv3 counter summary, if it was
@@ -216,7 +236,15 @@ def adjoint_leg(precision: str = "fp32", nsteps: int = 500, window: int = 50) ->
     ste = prm["cp_s"][frz[0]] * (Tm - Tw) / prm["latent"][frz[0]]
     dJ_dSte = sum(dL[p] * (-prm["latent"][p] / ste) for p in frz)
     dJ_dTw = g["T_face"][0] + sum(dL[p] * (-prm["cp_s"][p] / ste) for p in frz)
+    rb = algorithmic_bytes_reverse(2, N, 8 if precision == "fp64" else 4)
+    rev_step_s = t["reverse_ms"] / nsteps * 1e-3
+    ncell = prm["nx"] * prm["ny"]
     return {"workload": f"compound {prm['nx']}x{prm['ny']} D2Q9 N={N}, start just above melting",
+            # both reverse passes against their algorithmic bytes (HBM bound)
+            "reverse_roofline": {"bound": "hbm", "bytes_per_cell": rb["reverse_step"],
+                                 "achieved": round(rb["reverse_step"] * ncell / rev_step_s / 1e9, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(rb["reverse_step"] * ncell / rev_step_s / 1e9 / HBM_PEAK_GBS, 4)},
             "steps": nsteps, "window": window, "precision": precision,
             "forward_ms": round(fwd, 2), "reverse_ms": round(bwd, 2),
             "ratio": round(bwd / fwd, 3),

@@ -53,3 +53,10 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_reverse_step_bytes_per_cell():
+    """Compound 512^2, N = 3, float32: 736 B/cell for the collide reverse
+    and 216 B/cell for the gather (their counters read 1.07x and 1.19x)."""
+    b = bench.algorithmic_bytes_reverse(2, 3, 4)
+    assert b["collide_reverse"] == 736 and b["gather"] == 216 and b["reverse_step"] == 952
