@@ -161,6 +161,63 @@ class BatchAdjoint:
             pass
 
 
+def relax_contact_angles(cases: list, max_steps: int = 20000, chunk: int = 1000, tol: float = 0.05,
+                         device: int = 0) -> tuple:
+    """Isothermal pre-relaxation of the droplets whose wall angle is not 90
+    degrees (a semicircle on the wall, the shape they start as, is the
+    equilibrium only at 90 degrees): those cases run together as one batch
+    with their cold face held at the initial temperature (so nothing
+    freezes) until the wetted length of each -- the freezing material on the
+    wall layer, sum_x psi -- changes by less than tol cells over chunk
+    steps, or until max_steps.  Returns (states, steps, lengths): one device
+    state per case (None where theta = 90 degrees) to start the cooled run
+    from with Solver.lbf_state_from_device, the steps taken and each case's
+    last two wetted lengths."""
+    import copy as _copy
+
+    import torch
+
+    idx = [k for k, c in enumerate(cases) if abs(c.get("theta_deg", 90.0) - 90.0) > 1e-9]
+    states = [None] * len(cases)
+    if not idx:
+        return states, 0, {}
+    solvers = []
+    for k in idx:
+        prm = _copy.deepcopy(cases[k]["params"])
+        prm["T_face"] = [float(np.max(cases[k]["T"])), prm["T_face"][1]]
+        s = Solver(prm, device=device)
+        s.init_case(cases[k])
+        solvers.append(s)
+    b = Batch(solvers)
+
+    def wetted(s):
+        phi = s.lbf_get_moments(mask=1)["phi"]  # LBF_M_PHI
+        frz = [p for p in range(s.N) if s.params["freezes"][p]]
+        wall = phi[:, 0, 0, :] if s.dim == 2 else phi[:, 0]
+        return float(sum(wall[p].sum() for p in frz))
+
+    last = [wetted(s) for s in solvers]
+    steps, lengths = 0, {}
+    while steps < max_steps:
+        b.step(chunk)
+        b.synchronize()
+        steps += chunk
+        cur = [wetted(s) for s in solvers]
+        lengths = {idx[j]: (last[j], cur[j]) for j in range(len(idx))}
+        done = all(abs(c - l) < tol for c, l in zip(cur, last))
+        last = cur
+        if done:
+            break
+    b.close()
+    for j, k in enumerate(idx):
+        st = torch.empty(solvers[j].state_device_bytes(), dtype=torch.uint8, device=solvers[j].device)
+        solvers[j].lbf_state_to_device(st)
+        torch.cuda.synchronize(solvers[j].device)
+        states[k] = st
+        solvers[j].close()
+    return states, steps, lengths
+
+
 def batch_forward_with_checkpoints(batch: Batch, nsteps: int, window: int, graph: bool = False):
     """nsteps batched steps from the members' current states; returns the
     packed states at steps 0, window, 2 window, ... (one row each).  graph:
