@@ -281,6 +281,21 @@ lbf_status lbf_batch_set_tiles(lbf_batch* b, const int* tile);
  * so the states do not change) and keep the fastest; tile[4] receives the
  * choice (0 where the batch has no case of that N); tile may be NULL. */
 lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile);
+/* How the batched passes are launched (both flags off by default):
+ * LBF_BATCH_PERSISTENT launches each pass with a fixed number of blocks,
+ * each block striding over the pass's work items (moment blocks; collide
+ * tiles with their layer chunk) instead of one block per item: grid blocks
+ * (a positive multiple of 8), or with grid = 0 as many as the GPU holds at
+ * once (the kernel's occupancy times the compute units), never more than
+ * the items.  LBF_BATCH_CONCURRENT runs the phase-count groups on streams of
+ * their own, forked from and joined back to the batch's stream (parallel
+ * branches of a captured graph).  The states are bitwise the same in every
+ * mode.  Drops a captured graph; LBF_EINVAL for unknown flags or a grid that
+ * is negative or not a multiple of 8, LBF_EDEVICE if the side streams
+ * cannot be created. */
+#define LBF_BATCH_PERSISTENT 1u
+#define LBF_BATCH_CONCURRENT 2u
+lbf_status lbf_batch_set_launch(lbf_batch* b, unsigned flags, int grid);
 /* nsteps batched steps, launched one by one (asynchronous on the batch's
  * stream). */
 lbf_status lbf_batch_step(lbf_batch* b, int nsteps);

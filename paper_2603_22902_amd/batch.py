@@ -59,6 +59,14 @@ class Batch:
         self._check(lib().lbf_batch_tune(self._h, int(trial_steps), t))
         return {n: t[n - 1] for n in range(1, 5) if t[n - 1]}
 
+    def set_launch(self, persistent: bool = False, concurrent: bool = False, grid: int = 0) -> None:
+        """persistent: each pass launched with grid blocks (0: as many as the
+        GPU holds at once) striding over the work items; concurrent: the
+        phase-count groups on streams of their own (parallel graph
+        branches).  Drops a captured graph."""
+        flags = (1 if persistent else 0) | (2 if concurrent else 0)
+        self._check(lib().lbf_batch_set_launch(self._h, flags, int(grid)))
+
     def step(self, n: int = 1) -> None:
         self._check(lib().lbf_batch_step(self._h, int(n)))
 

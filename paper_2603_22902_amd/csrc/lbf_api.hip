@@ -55,6 +55,10 @@ struct lbf_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   int graph_parity;
+  unsigned launch;                // LBF_BATCH_PERSISTENT | LBF_BATCH_CONCURRENT
+  int grid;                       // persistent blocks per pass (0: the resident count)
+  hipStream_t side[lbf::MAXP];    // streams of the groups after the first (concurrent launch)
+  hipEvent_t fork, join[lbf::MAXP];
 };
 
 struct lbf_adj {
@@ -824,20 +828,46 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
 }
 
 // One batched step of every group at the given parity (the state buffers
-// read are cur0 ^ parity), or from packed batch state src to dst.
+// read are cur0 ^ parity), or from packed batch state src to dst.  With
+// LBF_BATCH_CONCURRENT the groups after the first run on side streams forked
+// from and joined back to the batch's stream (parallel branches when
+// captured).
 lbf_status batch_launch(lbf_batch* b, int parity, const void* src = nullptr, void* dst = nullptr) {
   lbf_ctx* c0 = b->first;
+  const int pers = (b->launch & LBF_BATCH_PERSISTENT) ? (b->grid > 0 ? b->grid : -1) : 0;
+  int ngroup = 0;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) ngroup += !b->g[gi].ctx.empty();
+  const bool conc = (b->launch & LBF_BATCH_CONCURRENT) && ngroup > 1;
+  if (conc) HIPCHK(c0, hipEventRecord(b->fork, b->stream), "hipEventRecord");
+  bool first = true;
   for (int gi = 0; gi < lbf::MAXP; ++gi) {
     lbf_batch_group& g = b->g[gi];
     if (g.ctx.empty()) continue;
     const lbf::Ops* ops = g.ctx[0]->ops;
     const int n = (int)g.ctx.size();
-    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, src, dst, b->stream),
-           "batched moments");
-    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, src, dst, b->stream),
-           "batched collide");
+    const bool side = conc && !first;
+    hipStream_t s = side ? b->side[gi] : b->stream;
+    first = false;
+    if (side) HIPCHK(c0, hipStreamWaitEvent(s, b->fork, 0), "hipStreamWaitEvent");
+    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, src, dst, pers, s), "batched moments");
+    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, src, dst, pers, s), "batched collide");
+    if (side) {
+      HIPCHK(c0, hipEventRecord(b->join[gi], s), "hipEventRecord");
+      HIPCHK(c0, hipStreamWaitEvent(b->stream, b->join[gi], 0), "hipStreamWaitEvent");
+    }
   }
   return LBF_OK;
+}
+
+void batch_release_streams(lbf_batch* b) {
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    if (b->side[gi]) (void)hipStreamDestroy(b->side[gi]);
+    if (b->join[gi]) (void)hipEventDestroy(b->join[gi]);
+    b->side[gi] = nullptr;
+    b->join[gi] = nullptr;
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  b->fork = nullptr;
 }
 
 lbf_status batch_check_members(lbf_batch* b) {
@@ -904,6 +934,13 @@ lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t b
   b->graph = nullptr;
   b->exec = nullptr;
   b->graph_parity = 0;
+  b->launch = 0;
+  b->grid = 0;
+  b->fork = nullptr;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    b->side[gi] = nullptr;
+    b->join[gi] = nullptr;
+  }
   size_t so = 0;
   for (int k = 0; k < n; ++k) {
     lbf_batch_group& g = b->g[ctxs[k]->N - 1];
@@ -943,6 +980,50 @@ lbf_status lbf_batch_set_tiles(lbf_batch* b, const int* tile) {
   return LBF_OK;
 }
 
+lbf_status lbf_batch_set_launch(lbf_batch* b, unsigned flags, int grid) {
+  if (!b) return LBF_EINVAL;
+  lbf_ctx* c0 = b->first;
+  if (flags & ~(LBF_BATCH_PERSISTENT | LBF_BATCH_CONCURRENT)) return fail(c0, LBF_EINVAL, "unknown launch flags");
+  if (grid < 0 || grid % 8) return fail(c0, LBF_EINVAL, "grid must be 0 or a positive multiple of 8");
+  if ((flags & LBF_BATCH_CONCURRENT) && !b->fork) {
+    int prev = 0;
+    HIPCHK(c0, hipGetDevice(&prev), "hipGetDevice");
+    HIPCHK(c0, hipSetDevice(c0->device), "hipSetDevice");
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int gi = 0; gi < lbf::MAXP && e == hipSuccess; ++gi) {
+      if (b->g[gi].ctx.empty()) continue;
+      e = hipStreamCreateWithFlags(&b->side[gi], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[gi], hipEventDisableTiming);
+    }
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+      batch_release_streams(b);
+      return hip_fail(c0, e, "side streams of a concurrent batch");
+    }
+  }
+  if ((flags & LBF_BATCH_PERSISTENT) && grid == 0) {
+    // Query the resident block counts of every pass, tile and state form now
+    // (no launch), not during a later graph capture.
+    char one = 0;
+    for (int gi = 0; gi < lbf::MAXP; ++gi) {
+      const lbf_batch_group& g = b->g[gi];
+      if (g.ctx.empty()) continue;
+      const lbf::Ops* ops = g.ctx[0]->ops;
+      for (int v = 0; v < 3; ++v)
+        for (int pass = 0; pass < 2; ++pass) {
+          HIPCHK(c0, ops->batch(pass, v, b->base + g.off, (int)g.ctx.size(), 0, 0, nullptr, nullptr, -1, b->stream),
+                 "occupancy query");
+          HIPCHK(c0, ops->batch(pass, v, b->base + g.off, (int)g.ctx.size(), 0, 0, &one, &one, -1, b->stream),
+                 "occupancy query");
+        }
+    }
+  }
+  batch_drop_graph(b);
+  b->launch = flags;
+  b->grid = grid;
+  return LBF_OK;
+}
+
 lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile) {
   if (!b) return LBF_EINVAL;
   if (trial_steps < 1) return fail(b->first, LBF_EINVAL, "trial_steps must be >= 1");
@@ -955,6 +1036,7 @@ lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile) {
     return fail(c0, LBF_EDEVICE, "hipEventCreate");
   }
   lbf_status result = LBF_OK;
+  const int pers = (b->launch & LBF_BATCH_PERSISTENT) ? (b->grid > 0 ? b->grid : -1) : 0;
   for (int gi = 0; gi < lbf::MAXP && result == LBF_OK; ++gi) {
     lbf_batch_group& g = b->g[gi];
     if (tile) tile[gi] = 0;
@@ -973,9 +1055,9 @@ lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile) {
       for (int rep = 0; rep <= trial_steps && e == hipSuccess; ++rep) {
         if (rep == 1) e = hipEventRecord(e0, b->stream);
         if (e == hipSuccess)
-          e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, nullptr, nullptr, b->stream);
+          e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, nullptr, nullptr, pers, b->stream);
         if (e == hipSuccess)
-          e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, nullptr, nullptr, b->stream);
+          e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, nullptr, nullptr, pers, b->stream);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1045,6 +1127,7 @@ lbf_status lbf_batch_replay(lbf_batch* b, int times) {
 lbf_status lbf_batch_destroy(lbf_batch* b) {
   if (!b) return LBF_OK;
   batch_drop_graph(b);
+  batch_release_streams(b);
   delete b;
   return LBF_OK;
 }

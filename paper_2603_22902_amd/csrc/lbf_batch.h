@@ -69,60 +69,73 @@ __device__ inline void batch_io(const BatchCase<S>& bc, int parity, const char* 
   }
 }
 
+// Both passes take their work items (moment blocks of MOMENT_THREADS cells;
+// collide tiles with their layer chunk) as item = blockIdx.x, blockIdx.x +
+// gridDim.x, ... below nitems.  Launched with one block per item the loop
+// runs once; a persistent launch (a fixed grid, a multiple of 8) strides
+// over the items, each block keeping items of one residue mod 8, so that the
+// XCD remap of the item index still gives every XCD a contiguous range of
+// tiles.
 template <class C, bool PACKED>
 __global__ void __launch_bounds__(MOMENT_THREADS)
-    batch_moment_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int parity,
+    batch_moment_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nitems, int parity,
                         const char* __restrict__ src, char* __restrict__ dst) {
   using S = typename C::S;
   __shared__ KParams P;
-  const int k = batch_case<S>(cs, ncase, blockIdx.x, false);
-  const BatchCase<S>& bc = cs[k];
-  load_params(P, bc.P);
-  StepArgs<S> a;
-  batch_io<S, PACKED>(bc, parity, src, dst, a);
-  const int cell = (blockIdx.x - bc.first_mblock) * MOMENT_THREADS + threadIdx.x;
-  if (cell < P.ncell) moment_cell<C>(a, P, cell);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int k = batch_case<S>(cs, ncase, it, false);
+    const BatchCase<S>& bc = cs[k];
+    if (it != (int)blockIdx.x) __syncthreads();  // every thread is done with the previous item's P
+    load_params(P, bc.P);
+    StepArgs<S> a;
+    batch_io<S, PACKED>(bc, parity, src, dst, a);
+    const int cell = (it - bc.first_mblock) * MOMENT_THREADS + threadIdx.x;
+    if (cell < P.ncell) moment_cell<C>(a, P, cell);
+  }
 }
 
 template <class C, bool PACKED>
 __global__ void __launch_bounds__(C::NT)
-    batch_collide_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nblocks, int parity,
+    batch_collide_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nitems, int parity,
                          const char* __restrict__ src, char* __restrict__ dst) {
   using S = typename C::S;
   __shared__ KParams P;
   __shared__ Smem<C> sm;
-  const int Lg = xcd_remap(blockIdx.x, nblocks);
-  const int k = batch_case<S>(cs, ncase, Lg, true);
-  const BatchCase<S>& bc = cs[k];
-  load_params(P, bc.P);
-  StepArgs<S> a;
-  batch_io<S, PACKED>(bc, parity, src, dst, a);
-  a.mom = a.aout;
-  a.mout = nullptr;
-  a.mfield = 0;
-  a.ntx = bc.ntx;
-  a.nty = bc.nty;
-  a.chunk = bc.chunk;
-  a.nblocks = bc.nblocks;
-  const BlockPos bp = block_pos_local<C>(a, P, Lg - bc.first_cblock);
   const int tid = threadIdx.x;
-  if (bp.w0 == 0) {
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, 0);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int Lg = xcd_remap(it, nitems);
+    const int k = batch_case<S>(cs, ncase, Lg, true);
+    const BatchCase<S>& bc = cs[k];
+    if (it != (int)blockIdx.x) __syncthreads();  // the previous item's P and ring are no longer read
+    load_params(P, bc.P);
+    StepArgs<S> a;
+    batch_io<S, PACKED>(bc, parity, src, dst, a);
+    a.mom = a.aout;
+    a.mout = nullptr;
+    a.mfield = 0;
+    a.ntx = bc.ntx;
+    a.nty = bc.nty;
+    a.chunk = bc.chunk;
+    a.nblocks = bc.nblocks;
+    const BlockPos bp = block_pos_local<C>(a, P, Lg - bc.first_cblock);
+    if (bp.w0 == 0) {
+      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, 0);
+      __syncthreads();
+      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, -1);
+    } else {
+      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
+      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
+    }
     __syncthreads();
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, -1);
-  } else {
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
-  }
-  __syncthreads();
-  for (int w = bp.w0; w < bp.w1; ++w) {
-    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
-    __syncthreads();
-    if (w == 0 || w == P.nwn - 1)
-      process_cell<C, false, true>(a, P, sm, bp, tid, w);
-    else
-      process_cell<C, false, false>(a, P, sm, bp, tid, w);
-    __syncthreads();
+    for (int w = bp.w0; w < bp.w1; ++w) {
+      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
+      __syncthreads();
+      if (w == 0 || w == P.nwn - 1)
+        process_cell<C, false, true>(a, P, sm, bp, tid, w);
+      else
+        process_cell<C, false, false>(a, P, sm, bp, tid, w);
+      __syncthreads();
+    }
   }
 }
 
@@ -141,44 +154,82 @@ inline void batch_geometry(const KParams& P, int tx, long long target, int& ntx,
   nblocks = (int)((long long)ntx * ((P.nwn + chunk - 1) / chunk));
 }
 
+// Blocks of kernel k (blockDim threads, static LDS only) that the whole GPU
+// holds at once, rounded down to a multiple of 8 (one per XCD); 0 on error.
+inline int resident_blocks(const void* k, int block) {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0) != hipSuccess) return 0;
+  return (per_cu * cus) / 8 * 8;
+}
+
+// Grid of a pass over nitems items.  grid = 0: one block per item; grid > 0
+// (a multiple of 8): that many persistent blocks; grid < 0: as many
+// persistent blocks as the GPU holds at once (the kernel's resident count).
+// Never more blocks than items.
+inline int batch_grid(int resident, int nitems, int grid) {
+  const int g = grid > 0 ? grid : (grid < 0 ? resident : 0);
+  return (g >= 8 && g < nitems) ? g : nitems;
+}
+
+// The resident block count is queried once per kernel, on its first launch
+// with grid < 0; nitems = 0 makes only that query (no launch), so that it
+// need not happen during a graph capture.
+template <class C, bool PACKED>
+inline hipError_t launch_collide_batch(const BatchCase<typename C::S>* cs, int ncase, int nitems, int parity,
+                                       const char* src, char* dst, int grid, hipStream_t s) {
+  int resident = 0;
+  if (grid < 0) {
+    static const int r = resident_blocks(reinterpret_cast<const void*>(&batch_collide_kernel<C, PACKED>), C::NT);
+    resident = r;
+  }
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL((batch_collide_kernel<C, PACKED>), dim3(batch_grid(resident, nitems, grid)), dim3(C::NT), 0, s,
+                     cs, ncase, nitems, parity, src, dst);
+  return hipGetLastError();
+}
+
 template <int NP, typename S, typename R, bool PACKED>
-inline hipError_t launch_batch_t(int pass, int variant, const BatchCase<S>* cs, int ncase, int nblocks, int parity,
-                                 const char* src, char* dst, hipStream_t s) {
+inline hipError_t launch_batch_t(int pass, int variant, const BatchCase<S>* cs, int ncase, int nitems, int parity,
+                                 const char* src, char* dst, int grid, hipStream_t s) {
   if (pass == 0) {
-    hipLaunchKernelGGL((batch_moment_kernel<Cfg<2, NP, S, R, 128, 1>, PACKED>), dim3(nblocks), dim3(MOMENT_THREADS),
-                       0, s, cs, ncase, parity, src, dst);
+    using C = Cfg<2, NP, S, R, 128, 1>;
+    int resident = 0;
+    if (grid < 0) {
+      static const int r =
+          resident_blocks(reinterpret_cast<const void*>(&batch_moment_kernel<C, PACKED>), MOMENT_THREADS);
+      resident = r;
+    }
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL((batch_moment_kernel<C, PACKED>), dim3(batch_grid(resident, nitems, grid)),
+                       dim3(MOMENT_THREADS), 0, s, cs, ncase, nitems, parity, src, dst);
     return hipGetLastError();
   }
   switch (variant) {
     case 0:
-      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 64, 1>, PACKED>), dim3(nblocks), dim3(64), 0, s, cs,
-                         ncase, nblocks, parity, src, dst);
-      break;
+      return launch_collide_batch<Cfg<2, NP, S, R, 64, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
     case 1:
-      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 128, 1>, PACKED>), dim3(nblocks), dim3(128), 0, s,
-                         cs, ncase, nblocks, parity, src, dst);
-      break;
+      return launch_collide_batch<Cfg<2, NP, S, R, 128, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
     case 2:
-      hipLaunchKernelGGL((batch_collide_kernel<Cfg<2, NP, S, R, 256, 1>, PACKED>), dim3(nblocks), dim3(256), 0, s,
-                         cs, ncase, nblocks, parity, src, dst);
-      break;
+      return launch_collide_batch<Cfg<2, NP, S, R, 256, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 // pass 0: moments, 1: collide; variant indexes BATCH_TILES.  With src and
 // dst (packed batch states) the step reads src and writes dst instead of
-// the cases' own buffers.
+// the cases' own buffers.  grid as batch_grid: 0 one block per item, else
+// persistent blocks striding over the items.
 template <int NP, typename S, typename R>
-inline hipError_t launch_batch(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
-                               const void* src, void* dst, hipStream_t s) {
+inline hipError_t launch_batch(int pass, int variant, const void* cases, int ncase, int nitems, int parity,
+                               const void* src, void* dst, int grid, hipStream_t s) {
   const auto* cs = static_cast<const BatchCase<S>*>(cases);
   if (src && dst)
-    return launch_batch_t<NP, S, R, true>(pass, variant, cs, ncase, nblocks, parity, static_cast<const char*>(src),
-                                          static_cast<char*>(dst), s);
+    return launch_batch_t<NP, S, R, true>(pass, variant, cs, ncase, nitems, parity, static_cast<const char*>(src),
+                                          static_cast<char*>(dst), grid, s);
   if (src || dst) return hipErrorInvalidValue;
-  return launch_batch_t<NP, S, R, false>(pass, variant, cs, ncase, nblocks, parity, nullptr, nullptr, s);
+  return launch_batch_t<NP, S, R, false>(pass, variant, cs, ncase, nitems, parity, nullptr, nullptr, grid, s);
 }
 
 }  // namespace lbf

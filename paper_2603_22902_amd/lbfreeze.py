@@ -83,6 +83,7 @@ def lib():
         L.lbf_batch_set_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.lbf_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.lbf_batch_step.argtypes = [vp, ctypes.c_int]
+        L.lbf_batch_set_launch.argtypes = [vp, ctypes.c_uint, ctypes.c_int]
         L.lbf_batch_capture.argtypes = [vp]
         L.lbf_batch_replay.argtypes = [vp, ctypes.c_int]
         L.lbf_batch_destroy.argtypes = [vp]
@@ -118,7 +119,7 @@ def lib():
                      "lbf_state_to_device", "lbf_state_from_device", "lbf_step_states", "lbf_adjoint_bytes",
                      "lbf_adjoint_create", "lbf_adjoint_seed", "lbf_adjoint_seed_objective", "lbf_adjoint_step", "lbf_adjoint_finish",
                      "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy",
-                     "lbf_batch_bytes", "lbf_batch_create", "lbf_batch_set_tiles", "lbf_batch_tune",
+                     "lbf_batch_bytes", "lbf_batch_create", "lbf_batch_set_tiles", "lbf_batch_set_launch", "lbf_batch_tune",
                      "lbf_batch_step", "lbf_batch_capture", "lbf_batch_replay", "lbf_batch_destroy",
                      "lbf_batch_state_bytes", "lbf_batch_state_to_device", "lbf_batch_step_states",
                      "lbf_batch_adjoint_bytes", "lbf_batch_adjoint_create", "lbf_batch_adjoint_seed",

@@ -63,6 +63,55 @@ def test_graph_replays_equal_eager_steps():
             assert np.array_equal(s.lbf_get_populations(), r.lbf_get_populations()), k
 
 
+@pytest.mark.parametrize("persistent,concurrent,grid", [(True, False, 0), (True, False, 16), (False, True, 0),
+                                                        (True, True, 24)])
+def test_launch_modes_equal_single_steps(persistent, concurrent, grid):
+    """Persistent blocks striding over the work items (the resident count,
+    or 16 and 24 blocks, so that every block takes many items of several
+    cases) and the phase-count groups on concurrent streams give bitwise
+    the states of single-case steps, eagerly, from graph replays and
+    between packed states."""
+    from paper_2603_22902_amd.batch import Batch
+    cases = _cases()
+    ref = _solvers(cases)
+    for s in ref:
+        s.lbf_step(6)
+    got = _solvers(cases)
+    b = Batch(got)
+    b.set_tiles({2: 64, 3: 128})
+    b.set_launch(persistent=persistent, concurrent=concurrent, grid=grid)
+    b.step(2)
+    b.capture()
+    b.replay(1)
+    b.step(1)
+    b.step(1)
+    b.synchronize()
+    for s, r in zip(got, ref):
+        assert s.step_count() == 6
+        assert np.array_equal(s.lbf_get_populations(), r.lbf_get_populations())
+        assert np.array_equal(s.lbf_get_aux(), r.lbf_get_aux())
+    # one packed step against the default launch's
+    src, d1, d2 = b.states(3)
+    b.state_to_device(src)
+    b.step_states(src, d1)
+    b.set_launch()
+    b.step_states(src, d2)
+    b.synchronize()
+    assert np.array_equal(d1.cpu().numpy(), d2.cpu().numpy())
+    b.close()
+
+
+def test_launch_grid_must_be_a_multiple_of_8():
+    from paper_2603_22902_amd.batch import Batch
+    from paper_2603_22902_amd.lbfreeze import LbfError, LBF_EINVAL
+    b = Batch(_solvers(_cases()[:2]))
+    for g in (12, -8):
+        with pytest.raises(LbfError) as e:
+            b.set_launch(persistent=True, grid=g)
+        assert e.value.status == LBF_EINVAL
+    b.close()
+
+
 def test_changing_tiles_after_capture_drops_the_graph():
     """lbf_batch_set_tiles rewrites the case tables a captured graph was
     built from: replay is refused (LBF_ESTATE) until the next capture, and
