@@ -317,6 +317,11 @@ lbf_status lbf_batch_destroy(lbf_batch* b);
  * touches the members' own states.  Asynchronous on the batch's stream. */
 lbf_status lbf_batch_state_bytes(const lbf_batch* b, size_t* bytes);
 lbf_status lbf_batch_state_to_device(lbf_batch* b, void* dst);
+/* The reverse copy: every member's current state becomes its slice of the
+ * packed state src (as lbf_state_from_device does per context), and its
+ * step count becomes steps.  Asynchronous on the batch's stream;
+ * LBF_EINVAL for a NULL or unaligned src or negative steps. */
+lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long steps);
 lbf_status lbf_batch_step_states(lbf_batch* b, const void* src, void* dst);
 
 /* Batched reverse step (2D, float32 or float64; the objectives and the

@@ -99,27 +99,40 @@ def _states(solver: Solver, k: int):
     return torch.empty((k, solver.state_device_bytes()), dtype=torch.uint8, device=solver.device)
 
 
+def last_window(nsteps: int, window: int) -> tuple:
+    """(number of checkpoints, first step of the last window, its length)."""
+    nck = (nsteps + window - 1) // window if nsteps > 0 else 1
+    start = (nck - 1) * window
+    return nck, start, nsteps - start
+
+
 def forward_with_checkpoints(solver: Solver, case: dict, nsteps: int, window: int):
     """Equilibrium start from case, nsteps steps; returns the device states
-    at steps 0, window, 2 window, ... (one row each)."""
+    at steps 0, window, 2 window, ... (one row each), followed by the states
+    of the last window after its checkpoint (x^{s+1} .. x^nsteps): the
+    reverse sweep goes through that window first and need not recompute
+    it.  The solver's own state ends at x^nsteps."""
     solver.init_case(case)
-    nck = (nsteps + window - 1) // window if nsteps > 0 else 1
-    ck = _states(solver, nck)
-    done = 0
-    for k in range(nck):
+    nck, start, n_last = last_window(nsteps, window)
+    ck = _states(solver, nck + n_last)
+    for k in range(nck - 1):
         solver.lbf_state_to_device(ck[k])
-        n = min(window, nsteps - done)
-        if n > 0:
-            solver.lbf_step(n)
-            done += n
+        solver.lbf_step(window)
+    solver.lbf_state_to_device(ck[nck - 1])
+    for j in range(n_last):
+        solver.lbf_step_states(ck[nck - 1 + j], ck[nck + j])
+    if n_last > 0:
+        solver.lbf_state_from_device(ck[nck + n_last - 1], nsteps)
     return ck
 
 
 def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = None,
                   objective: str = "frozen_fraction") -> tuple:
     """With the final state current: J and its gradient (dict) by the
-    reverse steps, re-running each window forward from its checkpoint
-    straight into a device tape (the solver's own state is not touched).
+    reverse steps.  The last window's states come with the checkpoints
+    (forward_with_checkpoints); every earlier window is re-run forward from
+    its checkpoint straight into a device tape (the solver's own state is
+    not touched), which reuses the last window's rows once those are done.
     timing (a dict) receives the milliseconds spent in recomputation and in
     reverse steps, measured with events on the solver's stream."""
     import torch
@@ -132,22 +145,26 @@ def reverse_sweep(solver: Solver, ck, nsteps: int, window: int, timing: dict = N
             e.record(solver.stream)
             ev.append(e)
 
+    nck, s_last, n_last = last_window(nsteps, window)
+    if ck.shape[0] != nck + n_last:
+        raise ValueError("checkpoints do not match nsteps and window (use forward_with_checkpoints)")
     adj = Adjoint(solver)
     J = adj.seed(objective)
-    final = _states(solver, 1)
-    solver.lbf_state_to_device(final[0])
-    tape = _states(solver, max(1, min(window, nsteps) - 1))
-    nck = ck.shape[0]
+    tape = None
     for k in range(nck - 1, -1, -1):
         start = k * window
         n = min(window, nsteps - start)
         if n <= 0:
             continue
-        nxt = ck[k + 1] if start + n < nsteps else final[0]
-        states = [ck[k]] + [tape[j] for j in range(n - 1)] + [nxt]
         mark()
-        for j in range(1, n):
-            solver.lbf_step_states(states[j - 1], states[j])
+        if k == nck - 1:
+            states = [ck[k + j] for j in range(n + 1)]
+        else:
+            if tape is None:
+                tape = ck[nck:nck + window - 1] if n_last >= window - 1 else _states(solver, window - 1)
+            states = [ck[k]] + [tape[j] for j in range(n - 1)] + [ck[k + 1]]
+            for j in range(1, n):
+                solver.lbf_step_states(states[j - 1], states[j])
         mark()
         for j in range(n - 1, -1, -1):
             adj.step(states[j], states[j + 1])

@@ -100,6 +100,10 @@ class Batch:
         """Copy every member's current state into the packed state dst."""
         self._check(lib().lbf_batch_state_to_device(self._h, ctypes.c_void_p(dst.data_ptr())))
 
+    def state_from_device(self, src, steps: int) -> None:
+        """Every member's state from the packed state src; step counts := steps."""
+        self._check(lib().lbf_batch_state_from_device(self._h, ctypes.c_void_p(src.data_ptr()), int(steps)))
+
     def step_states(self, src, dst) -> None:
         """One batched step from packed state src to dst (members untouched)."""
         self._check(lib().lbf_batch_step_states(self._h, ctypes.c_void_p(src.data_ptr()),
@@ -227,33 +231,44 @@ def relax_contact_angles(cases: list, max_steps: int = 20000, chunk: int = 1000,
 
 
 def batch_forward_with_checkpoints(batch: Batch, nsteps: int, window: int, graph: bool = False):
-    """nsteps batched steps from the members' current states; returns the
-    packed states at steps 0, window, 2 window, ... (one row each).  graph:
-    even stretches replay the captured two-step graph (capture first)."""
-    nck = (nsteps + window - 1) // window if nsteps > 0 else 1
-    ck = batch.states(nck)
-    done = 0
-    for k in range(nck):
+    """nsteps batched steps from the members' current states (taken as step
+    0); returns the packed states at steps 0, window, 2 window, ... (one row
+    each), followed by the packed states of the last window after its
+    checkpoint (x^{s+1} .. x^nsteps, batched steps between packed states),
+    which the reverse sweep then need not recompute.  The members end at
+    x^nsteps.  graph: the other windows' even stretches replay the captured
+    two-step graph (capture first)."""
+    from .adjoint import last_window
+
+    nck, start, n_last = last_window(nsteps, window)
+    ck = batch.states(nck + n_last)
+    for k in range(nck - 1):
         batch.state_to_device(ck[k])
-        n = min(window, nsteps - done)
-        if n > 0:
-            if graph:
-                batch.replay(n // 2)
-                batch.step(n % 2)
-            else:
-                batch.step(n)
-            done += n
+        if graph:
+            batch.replay(window // 2)
+            batch.step(window % 2)
+        else:
+            batch.step(window)
+    batch.state_to_device(ck[nck - 1])
+    for j in range(n_last):
+        batch.step_states(ck[nck - 1 + j], ck[nck + j])
+    if n_last > 0:
+        batch.state_from_device(ck[nck + n_last - 1], nsteps)
     return ck
 
 
 def batch_reverse_sweep(batch: Batch, ck, nsteps: int, window: int, objective: str = "frozen_fraction",
                         timing: dict = None) -> tuple:
-    """With the members at the final state: (J[ncase], grad[ncase, 22]) by
-    batched reverse steps, re-running each window from its checkpoint into a
-    packed tape with batched steps.  timing (a dict) receives the
+    """(J[ncase], grad[ncase, 22]) by batched reverse steps over the
+    checkpoints of :func:`batch_forward_with_checkpoints`: the last window's
+    packed states come with them; every earlier window is re-run from its
+    checkpoint into a packed tape with batched steps (reusing the last
+    window's rows once those are done).  timing (a dict) receives the
     milliseconds of recomputation and of reverse steps (events on the
     batch's stream)."""
     import torch
+
+    from .adjoint import last_window
 
     ev = []
 
@@ -263,21 +278,26 @@ def batch_reverse_sweep(batch: Batch, ck, nsteps: int, window: int, objective: s
             e.record(batch.stream)
             ev.append(e)
 
+    nck, s_last, n_last = last_window(nsteps, window)
+    if ck.shape[0] != nck + n_last:
+        raise ValueError("checkpoints do not match nsteps and window (use batch_forward_with_checkpoints)")
     adj = BatchAdjoint(batch)
-    final = batch.states(1)
-    batch.state_to_device(final[0])
-    J = adj.seed(final[0], objective)
-    tape = batch.states(max(1, min(window, nsteps) - 1))
-    for k in range(ck.shape[0] - 1, -1, -1):
+    J = adj.seed(ck[nck + n_last - 1], objective)
+    tape = None
+    for k in range(nck - 1, -1, -1):
         start = k * window
         n = min(window, nsteps - start)
         if n <= 0:
             continue
-        nxt = ck[k + 1] if start + n < nsteps else final[0]
-        states = [ck[k]] + [tape[j] for j in range(n - 1)] + [nxt]
         mark()
-        for j in range(1, n):
-            batch.step_states(states[j - 1], states[j])
+        if k == nck - 1:
+            states = [ck[k + j] for j in range(n + 1)]
+        else:
+            if tape is None:
+                tape = ck[nck:nck + window - 1] if n_last >= window - 1 else batch.states(window - 1)
+            states = [ck[k]] + [tape[j] for j in range(n - 1)] + [ck[k + 1]]
+            for j in range(1, n):
+                batch.step_states(states[j - 1], states[j])
         mark()
         for j in range(n - 1, -1, -1):
             adj.step(states[j], states[j + 1])

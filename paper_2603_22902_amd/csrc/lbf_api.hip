@@ -1160,6 +1160,31 @@ lbf_status lbf_batch_state_to_device(lbf_batch* b, void* dst) {
   return LBF_OK;
 }
 
+lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long steps) {
+  if (!b) return LBF_EINVAL;
+  lbf_ctx* c0 = b->first;
+  if (!src || (reinterpret_cast<uintptr_t>(src) & 255))
+    return fail(c0, LBF_EINVAL, "src must be a 256-byte aligned device buffer");
+  if (steps < 0) return fail(c0, LBF_EINVAL, "steps must be >= 0");
+  ADJCHK(batch_check_members(b));
+  const char* s = static_cast<const char*>(src);
+  for (int gi = 0; gi < lbf::MAXP; ++gi) {
+    lbf_batch_group& g = b->g[gi];
+    for (size_t k = 0; k < g.ctx.size(); ++k) {
+      lbf_ctx* c = g.ctx[k];
+      const int cur = g.cur0[k] ^ b->parity;
+      HIPCHK(c0, hipMemcpyAsync(pop_ptr(c, cur), s + g.soff[k], c->lay.pop_bytes, hipMemcpyDeviceToDevice, b->stream),
+             "hipMemcpyAsync");
+      HIPCHK(c0, hipMemcpyAsync(aux_ptr(c, cur), s + g.soff[k] + c->lay.pop_bytes, c->lay.aux_bytes,
+                                hipMemcpyDeviceToDevice, b->stream),
+             "hipMemcpyAsync");
+      c->steps = steps;
+      c->nan_flag = false;
+    }
+  }
+  return LBF_OK;
+}
+
 lbf_status lbf_batch_step_states(lbf_batch* b, const void* src, void* dst) {
   if (!b) return LBF_EINVAL;
   lbf_ctx* c0 = b->first;

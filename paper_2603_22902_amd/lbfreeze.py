@@ -89,6 +89,7 @@ def lib():
         L.lbf_batch_destroy.argtypes = [vp]
         L.lbf_batch_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_batch_state_to_device.argtypes = [vp, vp]
+        L.lbf_batch_state_from_device.argtypes = [vp, vp, ctypes.c_longlong]
         L.lbf_batch_step_states.argtypes = [vp, vp, vp]
         L.lbf_batch_adjoint_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbf_batch_adjoint_create.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
@@ -121,7 +122,7 @@ def lib():
                      "lbf_adjoint_gradient", "lbf_adjoint_state", "lbf_adjoint_destroy",
                      "lbf_batch_bytes", "lbf_batch_create", "lbf_batch_set_tiles", "lbf_batch_set_launch", "lbf_batch_tune",
                      "lbf_batch_step", "lbf_batch_capture", "lbf_batch_replay", "lbf_batch_destroy",
-                     "lbf_batch_state_bytes", "lbf_batch_state_to_device", "lbf_batch_step_states",
+                     "lbf_batch_state_bytes", "lbf_batch_state_to_device", "lbf_batch_state_from_device", "lbf_batch_step_states",
                      "lbf_batch_adjoint_bytes", "lbf_batch_adjoint_create", "lbf_batch_adjoint_seed",
                      "lbf_batch_adjoint_step", "lbf_batch_adjoint_finish", "lbf_batch_adjoint_gradient",
                      "lbf_batch_adjoint_destroy", "lbf_bandwidth_probe"):
