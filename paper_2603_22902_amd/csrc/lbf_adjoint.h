@@ -471,16 +471,23 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     return adj_pop<C>(lpin, lain, lattice, Lt::opp(i), cell, nc);
   };
 
+  // Each lattice's Q output adjoints are loaded together before its loop,
+  // and every direction runs the same code (no test for a zero adjoint), so
+  // the loads issue as one batch.
+  R abv[Q];
+  int facev[Q];
+
   // -- enthalpy LB and its face rules --
   R hb[Q];
   for (int i = 0; i < Q; ++i) hb[i] = R(0);
   R ETb = R(0), CTb = R(0), ithb = R(0), hfacb = R(0), Tb = R(0), rhocpb = R(0);
   double rhoHb = 0.0;
+  for (int i = 0; i < Q; ++i) abv[i] = out_adj(lh, i, facev[i]);
   for (int i = 0; i < Q; ++i) {
     const R wi = wgt<R, DIM>(i);
     const R cu = cdot<C>(i, u);
-    int face;
-    const R ab = out_adj(lh, i, face);
+    const int face = facev[i];
+    const R ab = abv[i];
     R postb = R(0);
     if (face < 0 || (face_flow(P, face) == BC_WALL && face_therm(P, face) == TBC_ADIABATIC)) {
       postb = ab;
@@ -524,7 +531,6 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
       for (int d = 0; d < DIM; ++d) ub[d] += cub2 * R(Lt::c(i, d));
       uub += -R(1.5) * Kbb;
     }
-    if (postb == R(0)) continue;
     if (i == 0) {
       // post = h0 - (h0 - he0) ith + (1 - ith/2) H0 (float64 in the forward)
       const R he0 = R(rhoH - double(Eref) * Td + double(w0) * (double(Eref) * Td - 1.5 * double(rhocp) * Td * double(uu)));
@@ -591,11 +597,12 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     for (int i = 0; i < Q; ++i) gb[i] = R(0);
     for (int d = 0; d < DIM; ++d) dpub[d] = R(0);
     R phDb = R(0);
+    for (int i = 0; i < Q; ++i) abv[i] = out_adj(l, i, facev[i]);
     for (int i = 0; i < Q; ++i) {
       const R wi = wgt<R, DIM>(i);
       const R cu = cdot<C>(i, u);
-      int face;
-      const R ab = out_adj(l, i, face);
+      const int face = facev[i];
+      const R ab = abv[i];
       R postb = R(0);
       if (face < 0 || face_flow(P, face) == BC_WALL) {
         postb = ab;
@@ -609,7 +616,6 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
         const R cub = gebb * wb * phi[p] * (-R(3));
         for (int d = 0; d < DIM; ++d) ub[d] += cub * R(Lt::c(i, d));
       }
-      if (postb == R(0)) continue;
       gb[i] += postb * (R(1) - itg);
       const R geb = postb * itg;
       const R Gib = postb * gfac;
@@ -638,11 +644,12 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   R fb[Q];
   for (int i = 0; i < Q; ++i) fb[i] = R(0);
   R sfacb = R(0);
+  for (int i = 0; i < Q; ++i) abv[i] = out_adj(0, i, facev[i]);
   for (int i = 0; i < Q; ++i) {
     const R wi = wgt<R, DIM>(i);
     const R cu = cdot<C>(i, u);
-    int face;
-    const R ab = out_adj(0, i, face);
+    const int face = facev[i];
+    const R ab = abv[i];
     R postb = R(0);
     if (face < 0 || face_flow(P, face) == BC_WALL) {
       postb = ab;
@@ -656,7 +663,9 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
       rhob += ab * sb;
       R sbb = ab * rho;
       fb[ib] += ab * (R(1) - itf);
-      itfb += -ab * (fpop[ib] - feb);
+      // the cell's own f populations are read again here rather than kept
+      // in registers since the forward recompute
+      itfb += -ab * (R(plane(pin, ib, nc)[cell]) - feb);
       const R febb = -ab * (R(1) - itf);
       prb += febb * R(3) * wb;
       rhob += febb * sb;
@@ -665,7 +674,6 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
       for (int d = 0; d < DIM; ++d) ub[d] -= cubb * R(Lt::c(i, d));
       uub += -R(1.5) * sbb * wb;
     }
-    if (postb == R(0)) continue;
     const R cF = cdot<C>(i, Fa);
     const R cFs = cdot<C>(i, F);
     const R c2 = R(Lt::c(i, 0) * Lt::c(i, 0) + Lt::c(i, 1) * Lt::c(i, 1) + Lt::c(i, 2) * Lt::c(i, 2));
@@ -675,7 +683,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     const R fe = (i == 0) ? R(3) * pr * (w0 - R(1)) + rho * si : R(3) * pr * wi + rho * si;
     fb[i] += postb * (R(1) - itf);
     const R feb = postb * itf;
-    itfb += postb * (fe - fpop[i]);
+    itfb += postb * (fe - R(plane(pin, i, nc)[cell]));
     sfacb += postb * Fi;
     const R Fib = postb * sfac;
     prb += feb * ((i == 0) ? R(3) * (w0 - R(1)) : R(3) * wi);
