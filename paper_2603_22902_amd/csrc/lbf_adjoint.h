@@ -907,6 +907,12 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
   const R fs = m_fs<C>(a, cell, nc);
   const double rhoH = double(wplane(a, L::M_RHOH, nc)[cell]);
 
+  // values read at the end, loaded before any store of this cell
+  const R div = R(plane(a.ain, C::A_DIV, nc)[cell]);
+  const R lq = seed ? R(0) : wplane(a, L::L_Q, nc)[cell];
+  R lphv[NP];
+  for (int p = 0; p < NP; ++p) lphv[p] = seed ? R(0) : wplane(a, L::L_PHI + p, nc)[cell];
+  const R lfs = seed ? R(0) : wplane(a, L::L_FS, nc)[cell];
   R phib[NP], fsb = wplane(a, L::O_FS, nc)[cell], rhob = R(0), upb[DIM];
   for (int p = 0; p < NP; ++p) phib[p] = wplane(a, L::O_PHI + p, nc)[cell];
   for (int d = 0; d < DIM; ++d) upb[d] = seed ? R(0) : wplane(a, L::L_U + d, nc)[cell];
@@ -1004,7 +1010,6 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
     phib[p] += R(flb * dfl_dphi[p]);
     gpar[PAR_LATENT + p] += flb * dfl_dL[p];
   }
-  const R div = R(plane(a.ain, C::A_DIV, nc)[cell]);
   const R idiv = R(1) / (R(1) - R(0.5) * div);
   R Db = R(0);
   for (int p = 0; p < NP; ++p) {
@@ -1014,9 +1019,9 @@ __host__ __device__ inline void adj_gather_cell(const AdjArgs<C>& a, const KPara
   plane(a.laout, AdjScal<C>::HS, nc)[cell] = ST(R(rhoHb));
   if (seed)
     for (int k = 0; k < (NP + 2) * Q; ++k) plane(a.lpout, k, nc)[cell] = ST(0);
-  const R qb = (seed ? R(0) : wplane(a, L::L_Q, nc)[cell]) + R(0.5 * rhoHb);
-  for (int p = 0; p < NP; ++p) plane(a.laout, p, nc)[cell] = seed ? ST(0) : ST(wplane(a, L::L_PHI + p, nc)[cell]);
-  plane(a.laout, C::A_FS, nc)[cell] = seed ? ST(0) : ST(wplane(a, L::L_FS, nc)[cell]);
+  const R qb = lq + R(0.5 * rhoHb);
+  for (int p = 0; p < NP; ++p) plane(a.laout, p, nc)[cell] = ST(lphv[p]);
+  plane(a.laout, C::A_FS, nc)[cell] = ST(lfs);
   for (int d = 0; d < DIM; ++d) plane(a.laout, C::A_U + d, nc)[cell] = ST(upb[d]);
   plane(a.laout, C::A_DIV, nc)[cell] = ST(Db);
   plane(a.laout, C::A_Q, nc)[cell] = ST(qb);
