@@ -70,72 +70,94 @@ __device__ inline void batch_io(const BatchCase<S>& bc, int parity, const char* 
 }
 
 // Both passes take their work items (moment blocks of MOMENT_THREADS cells;
-// collide tiles with their layer chunk) as item = blockIdx.x, blockIdx.x +
-// gridDim.x, ... below nitems.  Launched with one block per item the loop
-// runs once; a persistent launch (a fixed grid, a multiple of 8) strides
-// over the items, each block keeping items of one residue mod 8, so that the
-// XCD remap of the item index still gives every XCD a contiguous range of
-// tiles.
+// collide tiles with their layer chunk) either one per block (PERSIST =
+// false: item = blockIdx.x) or, in a persistent launch (a fixed grid, a
+// multiple of 8), as item = blockIdx.x, blockIdx.x + gridDim.x, ... below
+// nitems: each block keeps the items of one residue mod 8, so that the XCD
+// remap of the item index still gives every XCD a contiguous range of
+// tiles.  The two forms are separate kernels: the loop costs the collide
+// pass registers (144 against 128 VGPRs for N = 3, one wave per SIMD less).
 template <class C, bool PACKED>
+__device__ __forceinline__ void batch_moment_item(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int it,
+                                         int parity, const char* __restrict__ src, char* __restrict__ dst,
+                                         KParams& P) {
+  using S = typename C::S;
+  const int k = batch_case<S>(cs, ncase, it, false);
+  const BatchCase<S>& bc = cs[k];
+  load_params(P, bc.P);
+  StepArgs<S> a;
+  batch_io<S, PACKED>(bc, parity, src, dst, a);
+  const int cell = (it - bc.first_mblock) * MOMENT_THREADS + threadIdx.x;
+  if (cell < P.ncell) moment_cell<C>(a, P, cell);
+}
+
+template <class C, bool PACKED, bool PERSIST>
 __global__ void __launch_bounds__(MOMENT_THREADS)
     batch_moment_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nitems, int parity,
                         const char* __restrict__ src, char* __restrict__ dst) {
-  using S = typename C::S;
   __shared__ KParams P;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int k = batch_case<S>(cs, ncase, it, false);
-    const BatchCase<S>& bc = cs[k];
-    if (it != (int)blockIdx.x) __syncthreads();  // every thread is done with the previous item's P
-    load_params(P, bc.P);
-    StepArgs<S> a;
-    batch_io<S, PACKED>(bc, parity, src, dst, a);
-    const int cell = (it - bc.first_mblock) * MOMENT_THREADS + threadIdx.x;
-    if (cell < P.ncell) moment_cell<C>(a, P, cell);
+  if constexpr (PERSIST) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+      if (it != (int)blockIdx.x) __syncthreads();  // every thread is done with the previous item's P
+      batch_moment_item<C, PACKED>(cs, ncase, it, parity, src, dst, P);
+    }
+  } else {
+    batch_moment_item<C, PACKED>(cs, ncase, blockIdx.x, parity, src, dst, P);
   }
 }
 
 template <class C, bool PACKED>
+__device__ __forceinline__ void batch_collide_item(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int Lg,
+                                          int parity, const char* __restrict__ src, char* __restrict__ dst,
+                                          KParams& P, Smem<C>& sm) {
+  using S = typename C::S;
+  const int k = batch_case<S>(cs, ncase, Lg, true);
+  const BatchCase<S>& bc = cs[k];
+  load_params(P, bc.P);
+  StepArgs<S> a;
+  batch_io<S, PACKED>(bc, parity, src, dst, a);
+  a.mom = a.aout;
+  a.mout = nullptr;
+  a.mfield = 0;
+  a.ntx = bc.ntx;
+  a.nty = bc.nty;
+  a.chunk = bc.chunk;
+  a.nblocks = bc.nblocks;
+  const BlockPos bp = block_pos_local<C>(a, P, Lg - bc.first_cblock);
+  const int tid = threadIdx.x;
+  if (bp.w0 == 0) {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, 0);
+    __syncthreads();
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, -1);
+  } else {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
+  }
+  __syncthreads();
+  for (int w = bp.w0; w < bp.w1; ++w) {
+    for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
+    __syncthreads();
+    if (w == 0 || w == P.nwn - 1)
+      process_cell<C, false, true>(a, P, sm, bp, tid, w);
+    else
+      process_cell<C, false, false>(a, P, sm, bp, tid, w);
+    __syncthreads();
+  }
+}
+
+template <class C, bool PACKED, bool PERSIST>
 __global__ void __launch_bounds__(C::NT)
     batch_collide_kernel(const BatchCase<typename C::S>* __restrict__ cs, int ncase, int nitems, int parity,
                          const char* __restrict__ src, char* __restrict__ dst) {
-  using S = typename C::S;
   __shared__ KParams P;
   __shared__ Smem<C> sm;
-  const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int Lg = xcd_remap(it, nitems);
-    const int k = batch_case<S>(cs, ncase, Lg, true);
-    const BatchCase<S>& bc = cs[k];
-    if (it != (int)blockIdx.x) __syncthreads();  // the previous item's P and ring are no longer read
-    load_params(P, bc.P);
-    StepArgs<S> a;
-    batch_io<S, PACKED>(bc, parity, src, dst, a);
-    a.mom = a.aout;
-    a.mout = nullptr;
-    a.mfield = 0;
-    a.ntx = bc.ntx;
-    a.nty = bc.nty;
-    a.chunk = bc.chunk;
-    a.nblocks = bc.nblocks;
-    const BlockPos bp = block_pos_local<C>(a, P, Lg - bc.first_cblock);
-    if (bp.w0 == 0) {
-      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, 0);
-      __syncthreads();
-      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, -1);
-    } else {
-      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0 - 1);
-      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, bp.w0);
+  if constexpr (PERSIST) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+      if (it != (int)blockIdx.x) __syncthreads();  // the previous item's P and ring are no longer read
+      batch_collide_item<C, PACKED>(cs, ncase, xcd_remap(it, nitems), parity, src, dst, P, sm);
     }
-    __syncthreads();
-    for (int w = bp.w0; w < bp.w1; ++w) {
-      for (int f = tid; f < C::F; f += C::NT) fill_layer_cell<C>(a, P, sm, bp, f, w + 1);
-      __syncthreads();
-      if (w == 0 || w == P.nwn - 1)
-        process_cell<C, false, true>(a, P, sm, bp, tid, w);
-      else
-        process_cell<C, false, false>(a, P, sm, bp, tid, w);
-      __syncthreads();
-    }
+  } else {
+    batch_collide_item<C, PACKED>(cs, ncase, xcd_remap(blockIdx.x, nitems), parity, src, dst, P, sm);
   }
 }
 
@@ -179,14 +201,21 @@ inline int batch_grid(int resident, int nitems, int grid) {
 template <class C, bool PACKED>
 inline hipError_t launch_collide_batch(const BatchCase<typename C::S>* cs, int ncase, int nitems, int parity,
                                        const char* src, char* dst, int grid, hipStream_t s) {
+  if (grid == 0) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL((batch_collide_kernel<C, PACKED, false>), dim3(nitems), dim3(C::NT), 0, s, cs, ncase, nitems,
+                       parity, src, dst);
+    return hipGetLastError();
+  }
   int resident = 0;
   if (grid < 0) {
-    static const int r = resident_blocks(reinterpret_cast<const void*>(&batch_collide_kernel<C, PACKED>), C::NT);
+    static const int r =
+        resident_blocks(reinterpret_cast<const void*>(&batch_collide_kernel<C, PACKED, true>), C::NT);
     resident = r;
   }
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL((batch_collide_kernel<C, PACKED>), dim3(batch_grid(resident, nitems, grid)), dim3(C::NT), 0, s,
-                     cs, ncase, nitems, parity, src, dst);
+  hipLaunchKernelGGL((batch_collide_kernel<C, PACKED, true>), dim3(batch_grid(resident, nitems, grid)), dim3(C::NT),
+                     0, s, cs, ncase, nitems, parity, src, dst);
   return hipGetLastError();
 }
 
@@ -195,24 +224,27 @@ inline hipError_t launch_batch_t(int pass, int variant, const BatchCase<S>* cs, 
                                  const char* src, char* dst, int grid, hipStream_t s) {
   if (pass == 0) {
     using C = Cfg<2, NP, S, R, 128, 1>;
+    if (grid == 0) {
+      if (nitems <= 0) return hipSuccess;
+      hipLaunchKernelGGL((batch_moment_kernel<C, PACKED, false>), dim3(nitems), dim3(MOMENT_THREADS), 0, s, cs,
+                         ncase, nitems, parity, src, dst);
+      return hipGetLastError();
+    }
     int resident = 0;
     if (grid < 0) {
       static const int r =
-          resident_blocks(reinterpret_cast<const void*>(&batch_moment_kernel<C, PACKED>), MOMENT_THREADS);
+          resident_blocks(reinterpret_cast<const void*>(&batch_moment_kernel<C, PACKED, true>), MOMENT_THREADS);
       resident = r;
     }
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL((batch_moment_kernel<C, PACKED>), dim3(batch_grid(resident, nitems, grid)),
+    hipLaunchKernelGGL((batch_moment_kernel<C, PACKED, true>), dim3(batch_grid(resident, nitems, grid)),
                        dim3(MOMENT_THREADS), 0, s, cs, ncase, nitems, parity, src, dst);
     return hipGetLastError();
   }
   switch (variant) {
-    case 0:
-      return launch_collide_batch<Cfg<2, NP, S, R, 64, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
-    case 1:
-      return launch_collide_batch<Cfg<2, NP, S, R, 128, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
-    case 2:
-      return launch_collide_batch<Cfg<2, NP, S, R, 256, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
+    case 0: return launch_collide_batch<Cfg<2, NP, S, R, 64, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
+    case 1: return launch_collide_batch<Cfg<2, NP, S, R, 128, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
+    case 2: return launch_collide_batch<Cfg<2, NP, S, R, 256, 1>, PACKED>(cs, ncase, nitems, parity, src, dst, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
