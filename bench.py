@@ -417,6 +417,11 @@ def batch_adjoint_leg(cases, solvers, tiles, nsteps: int, window: int) -> dict:
             "speedup_vs_looped": round(loop / (fwd + rev), 3),
             "gradients_bitwise_equal_looped": bool(all(np.array_equal(g[k], gl[k]) for k in range(len(gl)))),
             "full_tape": full,
+            # what adjoint.choose_window's policy takes for this batch: the
+            # whole trajectory in HBM when it fits, else the checkpoints
+            "default_window": "full tape" if full and "ratio_vs_graph_forward" in full else window,
+            "ratio_default_window": (full["ratio_vs_graph_forward"] if full and "ratio_vs_graph_forward" in full
+                                     else round(rev / fwd, 3)),
             "J_range": [float(J.min()), float(J.max())]}
 
 
