@@ -319,9 +319,10 @@ lbf_status lbf_batch_state_bytes(const lbf_batch* b, size_t* bytes);
 lbf_status lbf_batch_state_to_device(lbf_batch* b, void* dst);
 /* The reverse copy: every member's current state becomes its slice of the
  * packed state src (as lbf_state_from_device does per context), and its
- * step count becomes steps.  Asynchronous on the batch's stream;
- * LBF_EINVAL for a NULL or unaligned src or negative steps. */
-lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long steps);
+ * step count advances by advance (how many steps src is ahead of the
+ * members' current states).  Asynchronous on the batch's stream;
+ * LBF_EINVAL for a NULL or unaligned src or a negative advance. */
+lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long advance);
 lbf_status lbf_batch_step_states(lbf_batch* b, const void* src, void* dst);
 
 /* Batched reverse step (2D, float32 or float64; the objectives and the

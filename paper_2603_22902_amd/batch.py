@@ -100,9 +100,11 @@ class Batch:
         """Copy every member's current state into the packed state dst."""
         self._check(lib().lbf_batch_state_to_device(self._h, ctypes.c_void_p(dst.data_ptr())))
 
-    def state_from_device(self, src, steps: int) -> None:
-        """Every member's state from the packed state src; step counts := steps."""
-        self._check(lib().lbf_batch_state_from_device(self._h, ctypes.c_void_p(src.data_ptr()), int(steps)))
+    def state_from_device(self, src, advance: int) -> None:
+        """Every member's state from the packed state src, which is advance
+        steps ahead of the members' current states (their step counts
+        advance by that much)."""
+        self._check(lib().lbf_batch_state_from_device(self._h, ctypes.c_void_p(src.data_ptr()), int(advance)))
 
     def step_states(self, src, dst) -> None:
         """One batched step from packed state src to dst (members untouched)."""
@@ -253,7 +255,7 @@ def batch_forward_with_checkpoints(batch: Batch, nsteps: int, window: int, graph
     for j in range(n_last):
         batch.step_states(ck[nck - 1 + j], ck[nck + j])
     if n_last > 0:
-        batch.state_from_device(ck[nck + n_last - 1], nsteps)
+        batch.state_from_device(ck[nck + n_last - 1], n_last)
     return ck
 
 
@@ -344,3 +346,31 @@ def batch_reverse_from_tape(batch: Batch, tape, nsteps: int, objective: str = "f
         batch.synchronize()
         timing["reverse_ms"] = e0.elapsed_time(e1)
     return J, g
+
+
+def batch_choose_window(batch: Batch, nsteps: int, window=None) -> int:
+    """window as given, else 0 (every packed state of the run in a device
+    tape, no recomputation) when that tape fits in three quarters of the
+    free device memory, else checkpoints every 50 steps."""
+    if window is not None:
+        return int(window)
+    import torch
+    free, _ = torch.cuda.mem_get_info(batch.solvers[0].device)
+    return 0 if (nsteps + 1) * batch.state_bytes() < 0.75 * free else 50
+
+
+def batch_objective_and_gradient(batch: Batch, nsteps: int, window=None, objective: str = "frozen_fraction",
+                                 graph: bool = False) -> tuple:
+    """nsteps batched steps from the members' current states, then the
+    batched reverse sweep: (J[ncase], grad[ncase, 22]) of the objective
+    ("frozen_fraction" or "front").  window = 0 keeps every packed state in
+    HBM; None chooses that when it fits (batch_choose_window).  graph: the
+    checkpointed forward replays the captured two-step graph (capture
+    first).  The members end at step nsteps either way."""
+    window = batch_choose_window(batch, nsteps, window)
+    if window == 0:
+        tape = batch_forward_to_tape(batch, nsteps)
+        batch.state_from_device(tape[nsteps], nsteps)
+        return batch_reverse_from_tape(batch, tape, nsteps, objective=objective)
+    ck = batch_forward_with_checkpoints(batch, nsteps, window, graph=graph)
+    return batch_reverse_sweep(batch, ck, nsteps, window, objective=objective)

@@ -1160,12 +1160,12 @@ lbf_status lbf_batch_state_to_device(lbf_batch* b, void* dst) {
   return LBF_OK;
 }
 
-lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long steps) {
+lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long advance) {
   if (!b) return LBF_EINVAL;
   lbf_ctx* c0 = b->first;
   if (!src || (reinterpret_cast<uintptr_t>(src) & 255))
     return fail(c0, LBF_EINVAL, "src must be a 256-byte aligned device buffer");
-  if (steps < 0) return fail(c0, LBF_EINVAL, "steps must be >= 0");
+  if (advance < 0) return fail(c0, LBF_EINVAL, "advance must be >= 0");
   ADJCHK(batch_check_members(b));
   const char* s = static_cast<const char*>(src);
   for (int gi = 0; gi < lbf::MAXP; ++gi) {
@@ -1178,7 +1178,7 @@ lbf_status lbf_batch_state_from_device(lbf_batch* b, const void* src, long long 
       HIPCHK(c0, hipMemcpyAsync(aux_ptr(c, cur), s + g.soff[k] + c->lay.pop_bytes, c->lay.aux_bytes,
                                 hipMemcpyDeviceToDevice, b->stream),
              "hipMemcpyAsync");
-      c->steps = steps;
+      c->steps += advance;
       c->nan_flag = false;
     }
   }

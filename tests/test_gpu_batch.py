@@ -273,6 +273,33 @@ def test_batched_full_tape_equals_checkpointed():
     assert np.array_equal(J0, J1) and np.array_equal(g0, g1)
 
 
+@pytest.mark.parametrize("window", [None, 0, 5])
+def test_batched_gradient_entry_point_and_final_states(window):
+    """batch_objective_and_gradient under each window policy (None: the
+    full tape, which fits; 0: the full tape; 5: checkpoints with a ragged
+    last window) gives the same gradients bitwise, and leaves every member
+    at the state and step count of nsteps eager batched steps."""
+    from paper_2603_22902_amd.batch import Batch, batch_objective_and_gradient
+    cases = _adj_cases("fp32")
+    n = 12
+    ref = _solvers(cases)
+    rb = Batch(ref)
+    rb.step(n)
+    rb.synchronize()
+    b = Batch(_solvers(cases))
+    J, g = batch_objective_and_gradient(b, n, window)
+    b.synchronize()
+    for s, r in zip(b.solvers, ref):
+        assert s.step_count() == n
+        assert np.array_equal(s.lbf_get_populations(), r.lbf_get_populations())
+        assert np.array_equal(s.lbf_get_aux(), r.lbf_get_aux())
+    b.step(1)  # the members stay usable as a batch
+    b.close()
+    b = Batch(_solvers(cases))
+    J0, g0 = batch_objective_and_gradient(b, n, 4)
+    assert np.array_equal(J, J0) and np.array_equal(g, g0)
+
+
 def test_batched_adjoint_through_graph_replays():
     """The forward pass replayed from the captured graph gives the same
     batched gradient as eager steps."""
