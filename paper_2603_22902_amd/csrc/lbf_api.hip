@@ -55,6 +55,7 @@ struct lbf_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   int graph_parity;
+  char* own_base;                 // lowest address of the members' state buffers (table offsets)
   unsigned launch;                // LBF_BATCH_PERSISTENT | LBF_BATCH_CONCURRENT
   int grid;                       // persistent blocks per pass (0: the resident count)
   hipStream_t side[lbf::MAXP];    // streams of the groups after the first (concurrent launch)
@@ -768,7 +769,8 @@ lbf_status batch_validate(lbf_ctx* const* ctxs, int n, std::string& err) {
 // Case table of group g for row tile variant v: geometry per case (about
 // 4096 collide blocks over the group, split by cell counts), block offsets.
 template <typename S>
-void batch_table(const lbf_batch_group& g, int v, std::vector<lbf::BatchCase<S>>& t, int& cblocks, int& mblocks) {
+void batch_table(const lbf_batch_group& g, int v, const char* own_base, std::vector<lbf::BatchCase<S>>& t,
+                 int& cblocks, int& mblocks) {
   long long total = 0;
   for (lbf_ctx* c : g.ctx) total += c->ncell;
   t.resize(g.ctx.size());
@@ -780,8 +782,8 @@ void batch_table(const lbf_batch_group& g, int v, std::vector<lbf::BatchCase<S>>
     b.soff = g.soff[k];
     b.pop_bytes = (long long)c->lay.pop_bytes;
     for (int j = 0; j < 2; ++j) {
-      b.pop[j] = static_cast<S*>(pop_ptr(c, j));
-      b.aux[j] = static_cast<S*>(aux_ptr(c, j));
+      b.pop_off[j] = static_cast<const char*>(pop_ptr(c, j)) - own_base;
+      b.aux_off[j] = static_cast<const char*>(aux_ptr(c, j)) - own_base;
     }
     b.cur = g.cur0[k];
     const long long target = (4096LL * c->ncell + total - 1) / total;
@@ -812,13 +814,13 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
   batch_drop_graph(b);
   if (c0->prm.precision == LBF_FP64) {
     std::vector<lbf::BatchCase<double>> t;
-    batch_table<double>(g, v, t, g.cblocks, g.mblocks);
+    batch_table<double>(g, v, b->own_base, t, g.cblocks, g.mblocks);
     HIPCHK(c0, hipMemcpyAsync(dst, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
            "hipMemcpyAsync");
     HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   } else {
     std::vector<lbf::BatchCase<float>> t;
-    batch_table<float>(g, v, t, g.cblocks, g.mblocks);
+    batch_table<float>(g, v, b->own_base, t, g.cblocks, g.mblocks);
     HIPCHK(c0, hipMemcpyAsync(dst, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
            "hipMemcpyAsync");
     HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -828,12 +830,15 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
 }
 
 // One batched step of every group at the given parity (the state buffers
-// read are cur0 ^ parity), or from packed batch state src to dst.  With
+// read are cur0 ^ parity, at their table offsets from own_base), or from
+// packed batch state src to dst.  With
 // LBF_BATCH_CONCURRENT the groups after the first run on side streams forked
 // from and joined back to the batch's stream (parallel branches when
 // captured).
 lbf_status batch_launch(lbf_batch* b, int parity, const void* src = nullptr, void* dst = nullptr) {
   lbf_ctx* c0 = b->first;
+  const bool packed = src && dst;
+  if (!packed) src = dst = b->own_base;
   const int pers = (b->launch & LBF_BATCH_PERSISTENT) ? (b->grid > 0 ? b->grid : -1) : 0;
   int ngroup = 0;
   for (int gi = 0; gi < lbf::MAXP; ++gi) ngroup += !b->g[gi].ctx.empty();
@@ -849,8 +854,10 @@ lbf_status batch_launch(lbf_batch* b, int parity, const void* src = nullptr, voi
     hipStream_t s = side ? b->side[gi] : b->stream;
     first = false;
     if (side) HIPCHK(c0, hipStreamWaitEvent(s, b->fork, 0), "hipStreamWaitEvent");
-    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, src, dst, pers, s), "batched moments");
-    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, src, dst, pers, s), "batched collide");
+    HIPCHK(c0, ops->batch(0, g.variant, b->base + g.off, n, g.mblocks, parity, src, dst, packed, pers, s),
+           "batched moments");
+    HIPCHK(c0, ops->batch(1, g.variant, b->base + g.off, n, g.cblocks, parity, src, dst, packed, pers, s),
+           "batched collide");
     if (side) {
       HIPCHK(c0, hipEventRecord(b->join[gi], s), "hipEventRecord");
       HIPCHK(c0, hipStreamWaitEvent(b->stream, b->join[gi], 0), "hipStreamWaitEvent");
@@ -934,6 +941,11 @@ lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t b
   b->graph = nullptr;
   b->exec = nullptr;
   b->graph_parity = 0;
+  b->own_base = nullptr;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < 2; ++j)
+      for (char* p : {static_cast<char*>(pop_ptr(ctxs[k], j)), static_cast<char*>(aux_ptr(ctxs[k], j))})
+        if (!b->own_base || p < b->own_base) b->own_base = p;
   b->launch = 0;
   b->grid = 0;
   b->fork = nullptr;
@@ -1011,10 +1023,10 @@ lbf_status lbf_batch_set_launch(lbf_batch* b, unsigned flags, int grid) {
       const lbf::Ops* ops = g.ctx[0]->ops;
       for (int v = 0; v < 3; ++v)
         for (int pass = 0; pass < 2; ++pass) {
-          HIPCHK(c0, ops->batch(pass, v, b->base + g.off, (int)g.ctx.size(), 0, 0, nullptr, nullptr, -1, b->stream),
-                 "occupancy query");
-          HIPCHK(c0, ops->batch(pass, v, b->base + g.off, (int)g.ctx.size(), 0, 0, &one, &one, -1, b->stream),
-                 "occupancy query");
+          for (int packed = 0; packed < 2; ++packed)
+            HIPCHK(c0, ops->batch(pass, v, b->base + g.off, (int)g.ctx.size(), 0, 0, &one, &one, packed != 0, -1,
+                                  b->stream),
+                   "occupancy query");
         }
     }
   }
@@ -1055,9 +1067,11 @@ lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile) {
       for (int rep = 0; rep <= trial_steps && e == hipSuccess; ++rep) {
         if (rep == 1) e = hipEventRecord(e0, b->stream);
         if (e == hipSuccess)
-          e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, nullptr, nullptr, pers, b->stream);
+          e = ops->batch(0, v, b->base + g.off, n, g.mblocks, b->parity, b->own_base, b->own_base, false, pers,
+                         b->stream);
         if (e == hipSuccess)
-          e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, nullptr, nullptr, pers, b->stream);
+          e = ops->batch(1, v, b->base + g.off, n, g.cblocks, b->parity, b->own_base, b->own_base, false, pers,
+                         b->stream);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1305,11 +1319,11 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
       bc.soff = g.soff[k];
       bc.pop_bytes = (long long)c->lay.pop_bytes;
       for (int j = 0; j < 2; ++j) {
-        bc.lp[j] = adj_lp(a, j);
-        bc.la[j] = adj_la(a, j);
+        bc.lp_off[j] = static_cast<char*>(adj_lp(a, j)) - ba->base;
+        bc.la_off[j] = static_cast<char*>(adj_la(a, j)) - ba->base;
       }
-      bc.work = adj_work(a);
-      bc.part = adj_part(a);
+      bc.work_off = static_cast<char*>(adj_work(a)) - ba->base;
+      bc.part_off = reinterpret_cast<char*>(adj_part(a)) - ba->base;
       // the single-case grids: one thread per cell for the collide reverse,
       // the step geometry for the tiled gather
       bc.cblocks = a->lay.cblocks;
@@ -1376,9 +1390,9 @@ lbf_status lbf_batch_adjoint_step(lbf_batch_adj* ba, const void* state, const vo
     if (!G.n) continue;
     const lbf::Ops* ops = b->g[gi].ctx[0]->ops;
     const int nb0 = lbf::collide_reverse_tiled(gi + 1) ? G.tblocks : G.cblocks;
-    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, nb0, state, next, ba->cur, b->stream),
+    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, nb0, state, next, ba->cur, ba->base, b->stream),
            "batched collide reverse");
-    HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, b->stream),
+    HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, ba->base, b->stream),
            "batched gather");
   }
   ba->cur ^= 1;

@@ -14,13 +14,18 @@
 namespace lbf {
 
 // One case of a batch.  Buffer cur holds the state at even batch steps.
-// soff, pop_bytes: where the case's state sits in a packed batch state (all
-// cases' device states, each laid out as lbf_state_to_device writes it).
+// pop_off, aux_off: the case's own two state buffers, as byte offsets from
+// the base address the kernels take as an argument.  (A pointer read from
+// the table would be generic to the compiler, which then emits flat memory
+// instructions; those count against the LDS counter too, so every wait for
+// an LDS read of the ring would also wait for the global traffic.  A
+// kernel argument plus an offset is known to be global.)  soff, pop_bytes:
+// where the case's state sits in a packed batch state (all cases' device
+// states, each laid out as lbf_state_to_device writes it).
 template <typename S>
 struct BatchCase {
   const KParams* P;  // device copy of the case's parameter block
-  S* pop[2];
-  S* aux[2];
+  long long pop_off[2], aux_off[2];
   long long soff, pop_bytes;
   int cur;
   int ntx, nty, chunk, nblocks;  // collide-pass geometry of this case
@@ -51,8 +56,9 @@ __device__ inline void load_params(KParams& dst, const KParams* src) {
   __syncthreads();
 }
 
-// Pointers of a case's step: its own buffers at the given parity, or
-// (PACKED) the case's slice of the packed batch states src -> dst.
+// Pointers of a case's step: its own buffers at the given parity (src and
+// dst are then both the base address of the offsets), or (PACKED) the
+// case's slice of the packed batch states src -> dst.
 template <typename S, bool PACKED>
 __device__ inline void batch_io(const BatchCase<S>& bc, int parity, const char* src, char* dst, StepArgs<S>& a) {
   if constexpr (PACKED) {
@@ -62,10 +68,10 @@ __device__ inline void batch_io(const BatchCase<S>& bc, int parity, const char* 
     a.aout = reinterpret_cast<S*>(dst + bc.soff + bc.pop_bytes);
   } else {
     const int in = bc.cur ^ parity;
-    a.pin = bc.pop[in];
-    a.pout = bc.pop[1 - in];
-    a.ain = bc.aux[in];
-    a.aout = bc.aux[1 - in];
+    a.pin = reinterpret_cast<const S*>(src + bc.pop_off[in]);
+    a.pout = reinterpret_cast<S*>(dst + bc.pop_off[1 - in]);
+    a.ain = reinterpret_cast<const S*>(src + bc.aux_off[in]);
+    a.aout = reinterpret_cast<S*>(dst + bc.aux_off[1 - in]);
   }
 }
 
@@ -249,19 +255,20 @@ inline hipError_t launch_batch_t(int pass, int variant, const BatchCase<S>* cs, 
   }
 }
 
-// pass 0: moments, 1: collide; variant indexes BATCH_TILES.  With src and
-// dst (packed batch states) the step reads src and writes dst instead of
-// the cases' own buffers.  grid as batch_grid: 0 one block per item, else
-// persistent blocks striding over the items.
+// pass 0: moments, 1: collide; variant indexes BATCH_TILES.  packed: the
+// step reads the packed batch state src and writes dst; else src = dst =
+// the base address of the cases' own-buffer offsets.  grid as batch_grid:
+// 0 one block per item, else persistent blocks striding over the items.
 template <int NP, typename S, typename R>
 inline hipError_t launch_batch(int pass, int variant, const void* cases, int ncase, int nitems, int parity,
-                               const void* src, void* dst, int grid, hipStream_t s) {
+                               const void* src, void* dst, bool packed, int grid, hipStream_t s) {
   const auto* cs = static_cast<const BatchCase<S>*>(cases);
-  if (src && dst)
+  if (!src || !dst) return hipErrorInvalidValue;
+  if (packed)
     return launch_batch_t<NP, S, R, true>(pass, variant, cs, ncase, nitems, parity, static_cast<const char*>(src),
                                           static_cast<char*>(dst), grid, s);
-  if (src || dst) return hipErrorInvalidValue;
-  return launch_batch_t<NP, S, R, false>(pass, variant, cs, ncase, nitems, parity, nullptr, nullptr, grid, s);
+  return launch_batch_t<NP, S, R, false>(pass, variant, cs, ncase, nitems, parity, static_cast<const char*>(src),
+                                         static_cast<char*>(dst), grid, s);
 }
 
 }  // namespace lbf

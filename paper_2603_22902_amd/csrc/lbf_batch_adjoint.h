@@ -19,13 +19,13 @@ namespace lbf {
 
 // One case of a batched reverse step.  The states x^n and x^{n+1} of a step
 // are packed batch states (soff, pop_bytes as in BatchCase); the adjoint
-// buffers are the case's own (layout of the single-case reverse step).
+// buffers are the case's own (layout of the single-case reverse step), given
+// as byte offsets from the batched adjoint buffer, whose address the
+// kernels take as an argument (global, not generic: see BatchCase).
 struct BatchAdjCase {
   long long soff, pop_bytes;
-  void* lp[2];
-  void* la[2];
-  void* work;
-  double* part;                       // gradient rows of the case
+  long long lp_off[2], la_off[2], work_off;
+  long long part_off;                 // gradient rows of the case
   int cblocks, first_cblock;          // one-thread-per-cell grid (collide reverse for N <= 2)
   int ntx, nty, chunk, nblocks;       // tile geometry of both passes (single-case step geometry)
   int first_tblock;
@@ -49,101 +49,108 @@ __device__ inline int batch_adj_case(const BatchAdjCase* cs, int ncase, int b, b
 // x^{n+1} = next); the adjoint of x^{n+1} is in buffers `parity`.
 template <class C>
 __device__ inline AdjArgs<C> batch_adj_args(const BatchAdjCase& bc, const char* state, const char* next,
-                                            int parity) {
+                                            int parity, char* abase) {
   using S = typename C::S;
   AdjArgs<C> a;
   a.pin = reinterpret_cast<const S*>(state + bc.soff);
   a.ain = reinterpret_cast<const S*>(state + bc.soff + bc.pop_bytes);
   a.mom = reinterpret_cast<const S*>(next + bc.soff + bc.pop_bytes);
-  a.lpin = static_cast<const S*>(bc.lp[parity]);
-  a.lain = static_cast<const S*>(bc.la[parity]);
-  a.lpout = static_cast<S*>(bc.lp[1 - parity]);
-  a.laout = static_cast<S*>(bc.la[1 - parity]);
-  a.work = static_cast<typename C::R*>(bc.work);
+  a.lpin = reinterpret_cast<const S*>(abase + bc.lp_off[parity]);
+  a.lain = reinterpret_cast<const S*>(abase + bc.la_off[parity]);
+  a.lpout = reinterpret_cast<S*>(abase + bc.lp_off[1 - parity]);
+  a.laout = reinterpret_cast<S*>(abase + bc.la_off[1 - parity]);
+  a.work = reinterpret_cast<typename C::R*>(abase + bc.work_off);
   return a;
+}
+
+__device__ inline double* batch_adj_part(const BatchAdjCase& bc, char* abase) {
+  return reinterpret_cast<double*>(abase + bc.part_off);
 }
 
 template <class C>
 __global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     batch_adj_collide_cell_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
-                                  const char* __restrict__ state, const char* __restrict__ next, int parity) {
+                                  const char* __restrict__ state, const char* __restrict__ next, int parity,
+                                  char* __restrict__ abase) {
   const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, blockIdx.x, true));
   const BatchAdjCase& bc = cs[k];
   const KParams& P = kpa[k];
-  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
+  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity, abase);
   double g[NPAR];
 #pragma unroll
   for (int j = 0; j < NPAR; ++j) g[j] = 0.0;
   const int lb = blockIdx.x - bc.first_cblock;
   const int cell = lb * ADJ_THREADS + threadIdx.x;
   if (cell < P.ncell) adj_collide_cell<C>(a, P, cell, g);
-  block_sum_to<NPAR, true>(g, bc.part + (long long)lb * NPAR);
+  block_sum_to<NPAR, true>(g, batch_adj_part(bc, abase) + (long long)lb * NPAR);
 }
 
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
     batch_adj_collide_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
                              int nblocks, const char* __restrict__ state, const char* __restrict__ next,
-                             int parity) {
+                             int parity, char* __restrict__ abase) {
   __shared__ Smem<C> sm;
   const int Lg = xcd_remap(blockIdx.x, nblocks);
   const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, false));
   const BatchAdjCase& bc = cs[k];
   const KParams& P = kpa[k];
-  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
+  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity, abase);
   const StepArgs<typename C::S> sa = fill_args<C>(a, bc.ntx, bc.nty, bc.chunk, bc.nblocks);
   const int t = Lg - bc.first_tblock;
-  collide_tile_block<C>(a, sa, P, block_pos_local<C>(sa, P, t), sm, bc.part + (long long)t * NPAR);
+  collide_tile_block<C>(a, sa, P, block_pos_local<C>(sa, P, t), sm, batch_adj_part(bc, abase) + (long long)t * NPAR);
 }
 
 template <class C>
 __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
     batch_adj_gather_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
                             int nblocks, const char* __restrict__ state, const char* __restrict__ next,
-                            int parity) {
+                            int parity, char* __restrict__ abase) {
   __shared__ FdaRing<C> ring;
   const int Lg = xcd_remap(blockIdx.x, nblocks);
   const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, false));
   const BatchAdjCase& bc = cs[k];
   const KParams& P = kpa[k];
-  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity);
+  const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity, abase);
   StepArgs<typename C::S> sa;
   sa.ntx = bc.ntx;
   sa.nty = bc.nty;
   sa.chunk = bc.chunk;
   sa.nblocks = bc.nblocks;
   const int t = Lg - bc.first_tblock;
-  gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, bc.part + (long long)t * NPAR);
+  gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, batch_adj_part(bc, abase) + (long long)t * NPAR);
 }
 
 // pass 0: collide reverse (over the cases' tiles for N >= 3, their 256-cell
 // blocks for N <= 2), 1: tiled gather over the cases' tiles; nblocks in
 // all.  cases: the case table followed, at the next 256-byte
 // boundary, by the cases' parameter blocks in table order, which the kernels
-// read through a restrict pointer (scalar loads, no LDS copy).
+// read through a restrict pointer (scalar loads, no LDS copy).  abase: the
+// batched adjoint buffer the table's offsets count from.
 inline size_t batch_adj_params_offset(int ncase) {
   return ((size_t)ncase * sizeof(BatchAdjCase) + 255) & ~size_t(255);
 }
 
 template <int NP, typename S, typename R>
 inline hipError_t launch_batch_adjoint(int pass, const void* cases, int ncase, int nblocks, const void* state,
-                                       const void* next, int parity, hipStream_t s) {
+                                       const void* next, int parity, void* abase, hipStream_t s) {
   using C = CfgOf<2, NP, S, R>;
   const auto* cs = static_cast<const BatchAdjCase*>(cases);
   const auto* kpa =
       reinterpret_cast<const KParams*>(static_cast<const char*>(cases) + batch_adj_params_offset(ncase));
   const char* st = static_cast<const char*>(state);
   const char* nx = static_cast<const char*>(next);
-  if (!st || !nx || nblocks < 1) return hipErrorInvalidValue;
+  char* ab = static_cast<char*>(abase);
+  if (!st || !nx || !ab || nblocks < 1) return hipErrorInvalidValue;
   if (pass == 0 && !collide_reverse_tiled(NP))
     hipLaunchKernelGGL((batch_adj_collide_cell_kernel<C>), dim3(nblocks), dim3(ADJ_THREADS), 0, s, cs, kpa, ncase,
-                       st, nx, parity);
+                       st, nx, parity, ab);
   else if (pass == 0)
     hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
-                       nx, parity);
+                       nx, parity, ab);
   else if (pass == 1)
     hipLaunchKernelGGL((batch_adj_gather_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
-                       nx, parity);
+                       nx, parity, ab);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

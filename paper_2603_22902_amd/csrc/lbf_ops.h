@@ -28,15 +28,16 @@ struct Ops {
                         const KParams* dP, double* part, double A, double B, hipStream_t s);
   // Batched passes over a case table (lbf_batch.h), 2D only (NULL in 3D):
   // pass 0 moments, 1 collide with row tile BATCH_TILES[variant]; with src
-  // and dst (packed batch states) from src to dst, else the cases' buffers;
-  // grid: 0 one block per work item, > 0 that many persistent blocks, < 0
-  // the resident block count (lbf_batch.h batch_grid).
+  // and dst (packed: packed batch states) from src to dst, else the cases'
+  // own buffers at offsets from src = dst; grid: 0 one block per work item,
+  // > 0 that many persistent blocks, < 0 the resident block count
+  // (lbf_batch.h batch_grid).
   hipError_t (*batch)(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
-                      const void* src, void* dst, int grid, hipStream_t s);
+                      const void* src, void* dst, bool packed, int grid, hipStream_t s);
   // Batched reverse-step passes (lbf_batch_adjoint.h): pass 0 collide
   // reverse, 1 tiled gather; NULL where the adjoint is not built.
   hipError_t (*batch_adjoint)(int pass, const void* cases, int ncase, int nblocks, const void* state,
-                              const void* next, int parity, hipStream_t s);
+                              const void* next, int parity, void* abase, hipStream_t s);
 };
 
 // dim 2 or 3, nphase 1..4; NULL if not built.  f32: float32 storage and
@@ -93,20 +94,20 @@ const Ops* ops_mix(int dim, int nphase);
         return hipErrorNotSupported;                                                             \
     }                                                                                            \
     static hipError_t batch(int pass, int variant, const void* cases, int ncase, int nblocks,    \
-                            int parity, const void* src, void* dst, int grid,                    \
+                            int parity, const void* src, void* dst, bool packed, int grid,       \
                             hipStream_t s) {                                                     \
       if constexpr (DIM == 2)                                                                    \
         return launch_batch<NP, ST, RT>(pass, variant, cases, ncase, nblocks, parity, src, dst,  \
-                                        grid, s);                                                \
+                                        packed, grid, s);                                        \
       else                                                                                       \
         return hipErrorNotSupported;                                                             \
     }                                                                                            \
     static hipError_t batch_adjoint(int pass, const void* cases, int ncase, int nblocks,         \
                                     const void* state, const void* next, int parity,             \
-                                    hipStream_t s) {                                             \
+                                    void* abase, hipStream_t s) {                                \
       if constexpr (ADJ && DIM == 2)                                                             \
         return launch_batch_adjoint<NP, ST, RT>(pass, cases, ncase, nblocks, state, next,        \
-                                                parity, s);                                      \
+                                                parity, abase, s);                               \
       else                                                                                       \
         return hipErrorNotSupported;                                                             \
     }                                                                                            \
