@@ -310,16 +310,16 @@ def batch_leg(nsteps: int = 200, precision: str = "fp32", adjoint: bool = True,
     b.replay(1)
     t_graph = timed(lambda: b.replay(nsteps // 2), b.stream)
     mlups = lambda ms: round(ncell * nsteps / (ms * 1e-3) / 1e6, 1)
-    # the same graph with persistent blocks (resident count, striding over
-    # the work items) and with the phase-count groups on parallel branches
-    modes = {"one_block_per_item": mlups(t_graph)}
-    for name, pers, conc in (("persistent", True, False), ("concurrent_groups", False, True),
-                             ("persistent_concurrent", True, True)):
+    # the same graph in each launch mode: one block per work item or
+    # persistent blocks (resident count, striding over the items), the
+    # phase-count groups on one stream or on parallel branches (the default)
+    modes = {}
+    for name, pers, conc in (("one_stream", False, False), ("persistent", True, False),
+                             ("concurrent_groups", False, True), ("persistent_concurrent", True, True)):
         b.set_launch(persistent=pers, concurrent=conc)
         b.capture()
         b.replay(1)
         modes[name] = mlups(timed(lambda: b.replay(nsteps // 2), b.stream))
-    b.set_launch()
     out = {"workload": f"{len(cases)} 2D cases, sides 64..512, N 2 or 3, {ncell} cells",
            "steps": nsteps, "precision": precision, "tiles": {str(k): v for k, v in tiles.items()},
            "mlups_graph": mlups(t_graph), "mlups_batch_eager": mlups(t_eager), "graph_launch_modes": modes,

@@ -281,7 +281,9 @@ lbf_status lbf_batch_set_tiles(lbf_batch* b, const int* tile);
  * so the states do not change) and keep the fastest; tile[4] receives the
  * choice (0 where the batch has no case of that N); tile may be NULL. */
 lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile);
-/* How the batched passes are launched (both flags off by default):
+/* How the batched passes are launched (lbf_batch_create sets
+ * LBF_BATCH_CONCURRENT when the batch holds more than one phase count, and
+ * nothing else):
  * LBF_BATCH_PERSISTENT launches each pass with a fixed number of blocks,
  * each block striding over the pass's work items (moment blocks; collide
  * tiles with their layer chunk) instead of one block per item: grid blocks

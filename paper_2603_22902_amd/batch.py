@@ -63,7 +63,8 @@ class Batch:
         """persistent: each pass launched with grid blocks (0: as many as the
         GPU holds at once) striding over the work items; concurrent: the
         phase-count groups on streams of their own (parallel graph
-        branches).  Drops a captured graph."""
+        branches; the creation default when there are several groups).
+        Drops a captured graph."""
         flags = (1 if persistent else 0) | (2 if concurrent else 0)
         self._check(lib().lbf_batch_set_launch(self._h, flags, int(grid)))
 

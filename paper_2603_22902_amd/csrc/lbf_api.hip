@@ -975,6 +975,17 @@ lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t b
       return s2;
     }
   }
+  // the phase-count groups on parallel streams when there is more than one
+  // (measured faster than one stream, and bitwise the same)
+  int ngroup = 0;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) ngroup += !b->g[gi].ctx.empty();
+  if (ngroup > 1) {
+    const lbf_status s3 = lbf_batch_set_launch(b, LBF_BATCH_CONCURRENT, 0);
+    if (s3 != LBF_OK) {
+      lbf_batch_destroy(b);
+      return s3;
+    }
+  }
   *out = b;
   return LBF_OK;
 }

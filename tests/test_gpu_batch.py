@@ -63,14 +63,14 @@ def test_graph_replays_equal_eager_steps():
             assert np.array_equal(s.lbf_get_populations(), r.lbf_get_populations()), k
 
 
-@pytest.mark.parametrize("persistent,concurrent,grid", [(True, False, 0), (True, False, 16), (False, True, 0),
-                                                        (True, True, 24)])
+@pytest.mark.parametrize("persistent,concurrent,grid", [(False, False, 0), (True, False, 0), (True, False, 16),
+                                                        (False, True, 0), (True, True, 24)])
 def test_launch_modes_equal_single_steps(persistent, concurrent, grid):
-    """Persistent blocks striding over the work items (the resident count,
-    or 16 and 24 blocks, so that every block takes many items of several
-    cases) and the phase-count groups on concurrent streams give bitwise
-    the states of single-case steps, eagerly, from graph replays and
-    between packed states."""
+    """One block per work item or persistent blocks striding over the items
+    (the resident count, or 16 and 24 blocks, so that every block takes
+    many items of several cases), the phase-count groups on one stream or
+    on concurrent ones (the default): bitwise the states of single-case
+    steps, eagerly, from graph replays and between packed states."""
     from paper_2603_22902_amd.batch import Batch
     cases = _cases()
     ref = _solvers(cases)
