@@ -533,6 +533,8 @@ def main():
     traffic = measured_traffic(args.workload, args.precision)
     step_ms = ms_mom + ms_col
     step_achieved = bpc["step"] * ncell / (step_ms * 1e-3) / 1e9
+    # the step's state bytes per second against the same box's copy rate
+    probe["step_state_vs_copy"] = round(step_achieved * 1e9 / bw["copy"], 3)
     step_traffic = measured_traffic(args.workload, args.precision, kernel="step")
     ms_per_step = ms_total / args.steps
     mlups = ncell * args.steps / (ms_total * 1e-3) / 1e6
