@@ -207,7 +207,9 @@ lbf_status lbf_step_states(lbf_ctx* ctx, const void* src, void* dst);
  * T_face[2], latent[4] and cos_theta[4][4] (each entry independent), through
  * every step of the run and the equilibrium start (lbf_init_fields with u
  * and p zero).  Built for dim = 2 with LBF_FP32 or LBF_FP64 (LBF_ENOTSUP
- * otherwise).  The inversion of eq. (H) and the regularised norm of the
+ * otherwise), for grids whose largest adjoint buffer spans less than 2 GiB
+ * (lbf_adjoint_bytes returns LBF_EINVAL beyond: about 3 150^2 cells in
+ * float32 with N = 4).  The inversion of eq. (H) and the regularised norm of the
  * pairwise normals are piecewise smooth: the derivative of the branch taken
  * is used.
  *

@@ -41,6 +41,8 @@
 // same code for the CPU checks against finite differences.
 #pragma once
 
+#include <type_traits>
+
 #include "lbf_step.h"
 
 namespace lbf {
@@ -87,6 +89,50 @@ template <class C>
 __host__ __device__ inline typename C::R* wplane(const AdjArgs<C>& a, int k, long long nc) {
   return a.work + (long long)k * nc;
 }
+
+// A buffer of nplanes planes of nc values, read and written through a
+// buffer resource on the device: the start and size sit in scalar
+// registers, and an access takes the plane's byte offset (the same for the
+// whole wave, in a scalar register) and the cell's (32-bit, per lane).
+// The hardware checks the range: outside the buffer a read gives 0 and a
+// write is dropped.  Against 64-bit per-lane addresses this frees the
+// registers of one address pair per access in flight.  The host (the
+// emulator) indexes the pointer.  Spans must stay below 2 GiB (checked with
+// the adjoint's layout).
+template <typename T>
+struct GBuf {
+  T* p;
+  int nc, bytes;
+  __host__ __device__ GBuf(T* ptr, long long ncell, int nplanes)
+      : p(ptr), nc((int)ncell), bytes((int)(ncell * nplanes * (long long)sizeof(T))) {}
+#if defined(__HIP_DEVICE_COMPILE__)
+  __device__ __amdgpu_buffer_rsrc_t rsrc() const {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(static_cast<const void*>(p)), 0, bytes, 0x00020000);
+  }
+#endif
+  __host__ __device__ typename std::remove_const<T>::type ld(int k, int i) const {
+    using U = typename std::remove_const<T>::type;
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(U) == 4)
+      return __builtin_bit_cast(U, __builtin_amdgcn_raw_buffer_load_b32(rsrc(), i * 4, k * nc * 4, 0));
+    else
+      return __builtin_bit_cast(U, __builtin_amdgcn_raw_buffer_load_b64(rsrc(), i * 8, k * nc * 8, 0));  // 2 dwords
+#else
+    return p[(long long)k * nc + i];
+#endif
+  }
+  __host__ __device__ void st(int k, int i, T v) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    using V2 = unsigned __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(T) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc(), i * 4, k * nc * 4, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), rsrc(), i * 8, k * nc * 8, 0);
+#else
+    p[(long long)k * nc + i] = v;
+#endif
+  }
+};
 
 // Planes of the per-cell population scalars in the adjoint of the lagged
 // fields (after the N + DIM + 3 planes of the forward layout).
@@ -282,6 +328,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   const int gx = lat % P.nx, gy = lat / P.nx;
   const ST* pin = a.pin;
   const ST* ain = a.ain;
+  const GBuf<const ST> bpi(pin, nc, (NP + 2) * Q), bai(ain, nc, C::NAUX);
 
   // ---- forward recompute (as process_cell) ----
   R phi[NP];
@@ -292,7 +339,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   for (int p = 0; p < NP; ++p)
     if (P.freezes[p]) psi += phi[p];
   R uprev[DIM];
-  for (int d = 0; d < DIM; ++d) uprev[d] = R(plane(ain, C::A_U + d, nc)[cell]);
+  for (int d = 0; d < DIM; ++d) uprev[d] = R(bai.ld(C::A_U + d, cell));
 
   R gphi[NP][DIM], lphi[NP], grho[DIM], gfp[NP][DIM], gu[DIM];
   for (int p = 0; p < NP; ++p) {
@@ -379,7 +426,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     F[d] = fsd + rho * R(P.grav[d]);
   }
   R fpop[Q];
-  for (int i = 0; i < Q; ++i) fpop[i] = R(plane(pin, i, nc)[cell]);
+  for (int i = 0; i < Q; ++i) fpop[i] = R(bpi.ld(i, cell));
   R mom[DIM];
   for (int d = 0; d < DIM; ++d) mom[d] = R(0);
   for (int i = 1; i < Q; ++i)
@@ -396,9 +443,9 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     u[d] = us[d] + R(0.5) * acc;
     Fa[d] = F[d] + rho * acc;
   }
-  const R fsp = R(plane(ain, C::A_FS, nc)[cell]);
+  const R fsp = R(bai.ld(C::A_FS, cell));
   R phip[NP];
-  for (int p = 0; p < NP; ++p) phip[p] = R(plane(ain, p, nc)[cell]);
+  for (int p = 0; p < NP; ++p) phip[p] = R(bai.ld(p, cell));
   R msum = R(0);
   for (int p = 0; p < NP; ++p) {
     if (!P.freezes[p]) continue;
@@ -430,9 +477,9 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   const R gfac = R(1) - R(0.5) * itg;
   const int lh = NP + 1;
   R hpop[Q];
-  for (int i = 0; i < Q; ++i) hpop[i] = R(plane(pin, lh * Q + i, nc)[cell]);
+  for (int i = 0; i < Q; ++i) hpop[i] = R(bpi.ld(lh * Q + i, cell));
   double Td, fl;
-  const double rhoH = own_enthalpy<C>(P, phi, hpop, R(plane(ain, C::A_Q, nc)[cell]), Td, fl);
+  const double rhoH = own_enthalpy<C>(P, phi, hpop, R(bai.ld(C::A_Q, cell)), Td, fl);
   const R T = R(Td);
   const R lam = mixture<R, NP>(phi, fs, P.lam_s, P.lam_l);
   const R cp = mixture<R, NP>(phi, fs, P.cp_s, P.cp_l);
@@ -456,19 +503,28 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   const ST* lain = a.lain;
   ST* lpout = a.lpout;
 
+  const GBuf<const ST> blp(lpin, nc, (NP + 2) * Q), bla(lain, nc, AdjScal<C>::NLA);
+  const GBuf<ST> blo(lpout, nc, (NP + 2) * Q);
+  const GBuf<R> bw(a.work, nc, L::NWORK);
+
   // adjoints of the lagged fields this cell wrote (u, D, q)
-  for (int d = 0; d < DIM; ++d) ub[d] += R(plane(lain, C::A_U + d, nc)[cell]);
-  Ddivb += R(plane(lain, C::A_DIV, nc)[cell]);
-  R HDb = R(plane(lain, C::A_Q, nc)[cell]);
+  for (int d = 0; d < DIM; ++d) ub[d] += R(bla.ld(C::A_U + d, cell));
+  Ddivb += R(bla.ld(C::A_DIV, cell));
+  R HDb = R(bla.ld(C::A_Q, cell));
 
   // Adjoint of the value written for direction i: at x + c_i for an inner
-  // link, or (face link) the opposite direction at this cell.
+  // link, or (face link) the opposite direction at this cell.  Both are
+  // addressed from the lower of the two planes, whose offset is then the
+  // same for the whole wave.
   auto out_adj = [&](int lattice, int i, int& face) -> R {
     int f2;
     const int t = push_index<C, true>(P, i, gx, gy, w, f2);
     face = f2;
-    if (t >= 0) return adj_pop<C>(lpin, lain, lattice, i, t, nc);
-    return adj_pop<C>(lpin, lain, lattice, Lt::opp(i), cell, nc);
+    const int ib = Lt::opp(i), k0 = i < ib ? i : ib;
+    const int idx = t >= 0 ? t + (i - k0) * (int)nc : cell + (ib - k0) * (int)nc;
+    R v = R(blp.ld(lattice * Q + k0, idx));
+    if (lattice >= 1) v += R(bla.ld(AdjScal<C>::GS + lattice - 1, t >= 0 ? t : cell));
+    return v;
   };
 
   // Each lattice's Q output adjoints are loaded together before its loop,
@@ -587,7 +643,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     for (int i = 0; i < Q; ++i) hb[i] += R(rhoHb);
     qpb += R(0.5 * rhoHb);
   }
-  for (int i = 0; i < Q; ++i) plane(lpout, lh * Q + i, nc)[cell] = ST(hb[i]);
+  for (int i = 0; i < Q; ++i) blo.st(lh * Q + i, cell, ST(hb[i]));
 
   // -- phase-field LBs --
   R Ddivb_g = R(0);
@@ -636,7 +692,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
       upb[d] -= R(3) * dpub[d] * phip[p];
       Rpb[p][d] += dpub[d];
     }
-    for (int i = 0; i < Q; ++i) plane(lpout, l * Q + i, nc)[cell] = ST(gb[i]);
+    for (int i = 0; i < Q; ++i) blo.st(l * Q + i, cell, ST(gb[i]));
   }
   Ddivb += Ddivb_g;
 
@@ -665,7 +721,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
       fb[ib] += ab * (R(1) - itf);
       // the cell's own f populations are read again here rather than kept
       // in registers since the forward recompute
-      itfb += -ab * (R(plane(pin, ib, nc)[cell]) - feb);
+      itfb += -ab * (R(bpi.ld(ib, cell)) - feb);
       const R febb = -ab * (R(1) - itf);
       prb += febb * R(3) * wb;
       rhob += febb * sb;
@@ -683,7 +739,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
     const R fe = (i == 0) ? R(3) * pr * (w0 - R(1)) + rho * si : R(3) * pr * wi + rho * si;
     fb[i] += postb * (R(1) - itf);
     const R feb = postb * itf;
-    itfb += postb * (fe - R(plane(pin, i, nc)[cell]));
+    itfb += postb * (fe - R(bpi.ld(i, cell)));
     sfacb += postb * Fi;
     const R Fib = postb * sfac;
     prb += feb * ((i == 0) ? R(3) * (w0 - R(1)) : R(3) * wi);
@@ -777,7 +833,7 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
   rhob += -irho * irho * irhob;
   for (int i = 1; i < Q; ++i)
     for (int d = 0; d < DIM; ++d) fb[i] += momb[d] * R(Lt::c(i, d));
-  for (int i = 0; i < Q; ++i) plane(lpout, i, nc)[cell] = ST(fb[i]);
+  for (int i = 0; i < Q; ++i) blo.st(i, cell, ST(fb[i]));
 
   // F = sum_p mu_p grad phi_p + rho g
   R mupb[NP], gphib[NP][DIM], lphib[NP];
@@ -840,22 +896,22 @@ __host__ __device__ inline void adj_collide_cell(const AdjArgs<C>& a, const KPar
 
   for (int p = 0; p < NP; ++p) {
     for (int d = 0; d < DIM; ++d) {
-      wplane(a, L::F_GPHI + p * DIM + d, nc)[cell] = gphib[p][d];
-      wplane(a, L::F_GFP + p * DIM + d, nc)[cell] = gfpb[p][d];
+      bw.st(L::F_GPHI + p * DIM + d, cell, gphib[p][d]);
+      bw.st(L::F_GFP + p * DIM + d, cell, gfpb[p][d]);
     }
-    wplane(a, L::F_LPHI + p, nc)[cell] = lphib[p];
-    wplane(a, L::O_PHI + p, nc)[cell] = phib[p];
-    wplane(a, L::L_PHI + p, nc)[cell] = phipb[p];
+    bw.st(L::F_LPHI + p, cell, lphib[p]);
+    bw.st(L::O_PHI + p, cell, phib[p]);
+    bw.st(L::L_PHI + p, cell, phipb[p]);
   }
   for (int d = 0; d < DIM; ++d) {
-    wplane(a, L::F_GRHO + d, nc)[cell] = grhob[d];
-    wplane(a, L::L_U + d, nc)[cell] = upb[d];
+    bw.st(L::F_GRHO + d, cell, grhob[d]);
+    bw.st(L::L_U + d, cell, upb[d]);
   }
-  wplane(a, L::F_DIV, nc)[cell] = Ddivb;
-  wplane(a, L::O_FS, nc)[cell] = fsb;
-  wplane(a, L::L_FS, nc)[cell] = fspb;
-  wplane(a, L::L_Q, nc)[cell] = qpb;
-  wplane(a, L::M_RHOH, nc)[cell] = R(rhoH);  // for pass 3 of this cell
+  bw.st(L::F_DIV, cell, Ddivb);
+  bw.st(L::O_FS, cell, fsb);
+  bw.st(L::L_FS, cell, fspb);
+  bw.st(L::L_Q, cell, qpb);
+  bw.st(L::M_RHOH, cell, R(rhoH));  // for pass 3 of this cell
 }
 
 template <class C>

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -556,6 +557,12 @@ lbf_status lbf_adjoint_bytes(const lbf_params* prm, size_t* bytes) {
   if (!bytes) return LBF_EINVAL;
   if (!lbf::check_params(prm).empty()) return LBF_EINVAL;
   if (prm->dim != 2 || prm->precision == LBF_MIXED) return LBF_ENOTSUP;
+  // the reverse passes address each buffer (population adjoints, lagged-field
+  // adjoints, work planes) through a buffer resource of a 31-bit span
+  const long long nc = (long long)prm->nx * prm->ny;
+  const long long elt = prm->precision == LBF_FP64 ? 8 : 4;
+  const long long planes = std::max<long long>((prm->nphase + 2) * 9, lbf::adj_nwork(prm->nphase, 2));
+  if (planes * nc * elt >= (1LL << 31)) return LBF_EINVAL;
   *bytes = lbf::make_adj_layout(prm, lbf::make_layout(prm)).total;
   return LBF_OK;
 }
@@ -1276,8 +1283,12 @@ extern "C" {
 lbf_status lbf_batch_adjoint_bytes(const lbf_batch* b, size_t* bytes) {
   if (!b || !bytes) return LBF_EINVAL;
   for (int gi = 0; gi < lbf::MAXP; ++gi)
-    for (lbf_ctx* c : b->g[gi].ctx)
+    for (lbf_ctx* c : b->g[gi].ctx) {
       if (!c->ops->batch_adjoint) return LBF_ENOTSUP;
+      size_t one = 0;
+      const lbf_status st = lbf_adjoint_bytes(&c->prm, &one);  // the single-case limits hold per case
+      if (st != LBF_OK) return st;
+    }
   *bytes = batch_adj_layout(b, nullptr, nullptr);
   return LBF_OK;
 }
