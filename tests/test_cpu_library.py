@@ -70,6 +70,35 @@ def test_state_bytes_covers_both_buffers():
     assert nb < 2 * 4 * nc * (6 * 19 + 10) + 8 * nc + (1 << 20)
 
 
+def test_adjoint_bytes_refuses_grids_beyond_its_buffer_spans():
+    """The reverse step reads and writes each buffer through a buffer
+    resource with a 31-bit span: lbf_adjoint_bytes sizes grids up to that
+    and refuses larger ones (LBF_EINVAL), 3D (LBF_ENOTSUP) and the mixed mode
+    (LBF_ENOTSUP) before any device work."""
+    import ctypes
+
+    L = lbfreeze.lib()
+
+    def adj_bytes(prm):
+        P = lbfreeze.make_params(prm)
+        n = ctypes.c_size_t(0)
+        return L.lbf_adjoint_bytes(ctypes.byref(P), ctypes.byref(n)), n.value
+
+    prm = synth.compound(precision="fp32")["params"]
+    st, nb = adj_bytes(prm)
+    assert st == lbfreeze.LBF_OK and nb > 0
+    # N = 3: the largest buffer holds (N + 2) 9 = 45 planes; 45 * 4 * nc < 2^31
+    ok, big = dict(prm), dict(prm)
+    ok["nx"] = ok["ny"] = 3400          # 45 * 4 * 3400^2 = 2.08e9 < 2^31
+    big["nx"] = big["ny"] = 3500        # 2.21e9 >= 2^31
+    assert adj_bytes(ok)[0] == lbfreeze.LBF_OK
+    assert adj_bytes(big)[0] == lbfreeze.LBF_EINVAL
+    f64 = dict(ok, precision="fp64")    # twice the bytes per value
+    assert adj_bytes(f64)[0] == lbfreeze.LBF_EINVAL
+    assert adj_bytes(dict(prm, precision="mixed"))[0] == lbfreeze.LBF_ENOTSUP
+    assert adj_bytes(synth.impurities(n=24)["params"])[0] == lbfreeze.LBF_ENOTSUP
+
+
 # ----- host emulator of the step kernel against the oracle ---------------
 EMU_CASES = [
     (2, (37, 29), 2, "fp64", ("wall", "wall"), ("dirichlet", "adiabatic"), 1e-3),
