@@ -268,7 +268,8 @@ lbf_status lbf_adjoint_destroy(lbf_adj* adj);
  * streams before batch calls.  Members must not be stepped on their own while
  * in the batch (LBF_ESTATE); lbf_batch_step and lbf_batch_replay update their
  * states and step counts.  The caller allocates lbf_batch_bytes of device
- * memory (256-byte aligned, case tables) for the batch's lifetime. */
+ * memory (256-byte aligned; the case tables and their block-to-case maps)
+ * for the batch's lifetime. */
 typedef struct lbf_batch lbf_batch;
 lbf_status lbf_batch_bytes(lbf_ctx* const* ctxs, int n, size_t* bytes);
 lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t bytes, void* hip_stream,

@@ -739,7 +739,35 @@ lbf_status lbf_adjoint_destroy(lbf_adj* a) {
 // ----- batched cases ---------------------------------------------------
 namespace {
 
-size_t batch_table_bytes(int n) { return lbf::align256((size_t)n * sizeof(lbf::BatchCase<float>)); }
+// Blocks of each pass of group g with row tile variant v (the geometry the
+// case table gets: about 4096 collide blocks over the group, split by cell
+// counts; moment blocks of MOMENT_THREADS cells).
+void batch_blocks(const std::vector<lbf_ctx*>& ctx, int v, long long& cblocks, long long& mblocks) {
+  long long total = 0;
+  for (lbf_ctx* c : ctx) total += c->ncell;
+  cblocks = mblocks = 0;
+  for (lbf_ctx* c : ctx) {
+    int ntx, chunk, nb;
+    lbf::batch_geometry(c->kp, lbf::BATCH_TILES[v], (4096LL * c->ncell + total - 1) / total, ntx, chunk, nb);
+    cblocks += nb;
+    mblocks += (c->ncell + lbf::MOMENT_THREADS - 1) / lbf::MOMENT_THREADS;
+  }
+}
+
+// Device bytes of a group's table: the cases, then the moment pass's
+// block-to-case map, then the collide pass's (sized for the tile variant
+// with the most blocks).
+size_t batch_table_bytes(const std::vector<lbf_ctx*>& ctx, long long* map_ints = nullptr) {
+  long long cmax = 0, mb = 0;
+  for (int v = 0; v < 3; ++v) {
+    long long cb, m;
+    batch_blocks(ctx, v, cb, m);
+    cmax = cb > cmax ? cb : cmax;
+    mb = m;
+  }
+  if (map_ints) *map_ints = mb + cmax;
+  return lbf::align256(ctx.size() * sizeof(lbf::BatchCase<float>) + (size_t)(mb + cmax) * sizeof(int));
+}
 
 lbf_status batch_validate(lbf_ctx* const* ctxs, int n, std::string& err) {
   if (!ctxs || n < 1) {
@@ -777,7 +805,7 @@ lbf_status batch_validate(lbf_ctx* const* ctxs, int n, std::string& err) {
 // 4096 collide blocks over the group, split by cell counts), block offsets.
 template <typename S>
 void batch_table(const lbf_batch_group& g, int v, const char* own_base, std::vector<lbf::BatchCase<S>>& t,
-                 int& cblocks, int& mblocks) {
+                 std::vector<int>& map, int& cblocks, int& mblocks) {
   long long total = 0;
   for (lbf_ctx* c : g.ctx) total += c->ncell;
   t.resize(g.ctx.size());
@@ -802,6 +830,16 @@ void batch_table(const lbf_batch_group& g, int v, const char* own_base, std::vec
     cblocks += b.nblocks;
     mblocks += b.mblocks;
   }
+  // block-to-case maps after the table: moment blocks, then collide blocks
+  static_assert(sizeof(lbf::BatchCase<S>) % sizeof(int) == 0, "maps follow the table in ints");
+  const int map0 = (int)(t.size() * sizeof(t[0]) / sizeof(int));
+  map.assign((size_t)mblocks + cblocks, 0);
+  for (size_t k = 0; k < t.size(); ++k) {
+    t[k].map_m = map0;
+    t[k].map_c = map0 + mblocks;
+    for (int j = 0; j < t[k].mblocks; ++j) map[t[k].first_mblock + j] = (int)k;
+    for (int j = 0; j < t[k].nblocks; ++j) map[mblocks + t[k].first_cblock + j] = (int)k;
+  }
 }
 
 // A captured graph holds the launches of the case tables it was captured
@@ -819,19 +857,25 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
   lbf_ctx* c0 = b->first;
   void* dst = b->base + g.off;
   batch_drop_graph(b);
+  std::vector<int> map;
+  std::vector<char> img;
+  auto pack = [&](const auto& t) {
+    const size_t tb = t.size() * sizeof(t[0]);
+    img.resize(tb + map.size() * sizeof(int));
+    memcpy(img.data(), t.data(), tb);
+    memcpy(img.data() + tb, map.data(), map.size() * sizeof(int));
+  };
   if (c0->prm.precision == LBF_FP64) {
     std::vector<lbf::BatchCase<double>> t;
-    batch_table<double>(g, v, b->own_base, t, g.cblocks, g.mblocks);
-    HIPCHK(c0, hipMemcpyAsync(dst, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
-           "hipMemcpyAsync");
-    HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    batch_table<double>(g, v, b->own_base, t, map, g.cblocks, g.mblocks);
+    pack(t);
   } else {
     std::vector<lbf::BatchCase<float>> t;
-    batch_table<float>(g, v, b->own_base, t, g.cblocks, g.mblocks);
-    HIPCHK(c0, hipMemcpyAsync(dst, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, b->stream),
-           "hipMemcpyAsync");
-    HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    batch_table<float>(g, v, b->own_base, t, map, g.cblocks, g.mblocks);
+    pack(t);
   }
+  HIPCHK(c0, hipMemcpyAsync(dst, img.data(), img.size(), hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
+  HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   g.variant = v;
   return LBF_OK;
 }
@@ -914,11 +958,11 @@ lbf_status lbf_batch_bytes(lbf_ctx* const* ctxs, int n, size_t* bytes) {
   std::string err;
   const lbf_status st = batch_validate(ctxs, n, err);
   if (st != LBF_OK) return st;
-  int cnt[lbf::MAXP] = {0, 0, 0, 0};
-  for (int k = 0; k < n; ++k) ++cnt[ctxs[k]->N - 1];
+  std::vector<lbf_ctx*> grp[lbf::MAXP];
+  for (int k = 0; k < n; ++k) grp[ctxs[k]->N - 1].push_back(ctxs[k]);
   size_t o = 0;
   for (int gi = 0; gi < lbf::MAXP; ++gi)
-    if (cnt[gi]) o += batch_table_bytes(cnt[gi]);
+    if (!grp[gi].empty()) o += batch_table_bytes(grp[gi]);
   *bytes = o;
   return LBF_OK;
 }
@@ -975,7 +1019,7 @@ lbf_status lbf_batch_create(lbf_ctx* const* ctxs, int n, void* dev_buf, size_t b
     lbf_batch_group& g = b->g[gi];
     if (g.ctx.empty()) continue;
     g.off = o;
-    o += batch_table_bytes((int)g.ctx.size());
+    o += batch_table_bytes(g.ctx);
     const lbf_status s2 = batch_set_variant(b, gi, 1);
     if (s2 != LBF_OK) {
       delete b;

@@ -1,7 +1,7 @@
 // Batched time step: many independent cases (different grid sizes and
 // parameters, one phase count N) advance together, each pass one launch over
-// all cases.  A block looks up its case in the case table (binary search over
-// the cases' first block numbers), copies the case's parameter block into LDS
+// all cases.  A block looks up its case in the pass's block-to-case map
+// (stored after the case table), copies the case's parameter block into LDS
 // and runs the same phase functions as the single-case kernels.  The result
 // of each case is bitwise that of its single-case step: the per-cell
 // arithmetic does not depend on the tile shape or on the batch.
@@ -31,21 +31,17 @@ struct BatchCase {
   int ntx, nty, chunk, nblocks;  // collide-pass geometry of this case
   int mblocks;                   // moments-pass blocks of this case
   int first_cblock, first_mblock;
+  int map_m, map_c;  // the block-to-case maps, in ints from the table's start (same in every case)
 };
 
-// Last case k with first[k] <= b (uniform across the block).
+// The case of block b of a pass: one entry of the pass's block-to-case map
+// (written with the table), which the table's first case locates.  Two
+// dependent scalar loads, where a binary search over the cases' first
+// blocks took one per level.
 template <typename S>
 __device__ inline int batch_case(const BatchCase<S>* cs, int ncase, int b, bool collide) {
-  int lo = 0, hi = ncase - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int f = collide ? cs[mid].first_cblock : cs[mid].first_mblock;
-    if (f <= b)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
+  const int* map = reinterpret_cast<const int*>(cs) + (collide ? cs[0].map_c : cs[0].map_m);
+  return map[b];
 }
 
 __device__ inline void load_params(KParams& dst, const KParams* src) {
