@@ -757,7 +757,7 @@ void batch_blocks(const std::vector<lbf_ctx*>& ctx, int v, long long& cblocks, l
 // Device bytes of a group's table: the cases, then the moment pass's
 // block-to-case map, then the collide pass's (sized for the tile variant
 // with the most blocks).
-size_t batch_table_bytes(const std::vector<lbf_ctx*>& ctx, long long* map_ints = nullptr) {
+size_t batch_table_bytes(const std::vector<lbf_ctx*>& ctx) {
   long long cmax = 0, mb = 0;
   for (int v = 0; v < 3; ++v) {
     long long cb, m;
@@ -765,7 +765,6 @@ size_t batch_table_bytes(const std::vector<lbf_ctx*>& ctx, long long* map_ints =
     cmax = cb > cmax ? cb : cmax;
     mb = m;
   }
-  if (map_ints) *map_ints = mb + cmax;
   return lbf::align256(ctx.size() * sizeof(lbf::BatchCase<float>) + (size_t)(mb + cmax) * sizeof(int));
 }
 
@@ -859,6 +858,7 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
   batch_drop_graph(b);
   std::vector<int> map;
   std::vector<char> img;
+  int cblocks = 0, mblocks = 0;
   auto pack = [&](const auto& t) {
     const size_t tb = t.size() * sizeof(t[0]);
     img.resize(tb + map.size() * sizeof(int));
@@ -867,15 +867,19 @@ lbf_status batch_set_variant(lbf_batch* b, int gi, int v) {
   };
   if (c0->prm.precision == LBF_FP64) {
     std::vector<lbf::BatchCase<double>> t;
-    batch_table<double>(g, v, b->own_base, t, map, g.cblocks, g.mblocks);
+    batch_table<double>(g, v, b->own_base, t, map, cblocks, mblocks);
     pack(t);
   } else {
     std::vector<lbf::BatchCase<float>> t;
-    batch_table<float>(g, v, b->own_base, t, map, g.cblocks, g.mblocks);
+    batch_table<float>(g, v, b->own_base, t, map, cblocks, mblocks);
     pack(t);
   }
+  if (img.size() > batch_table_bytes(g.ctx))  // the sizing and the table must agree on the geometry
+    return fail(c0, LBF_EINVAL, "batch case table larger than its reserved space");
   HIPCHK(c0, hipMemcpyAsync(dst, img.data(), img.size(), hipMemcpyHostToDevice, b->stream), "hipMemcpyAsync");
   HIPCHK(c0, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  g.cblocks = cblocks;
+  g.mblocks = mblocks;
   g.variant = v;
   return LBF_OK;
 }
