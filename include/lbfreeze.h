@@ -294,8 +294,9 @@ lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile);
  * once (the kernel's occupancy times the compute units), never more than
  * the items.  LBF_BATCH_CONCURRENT runs the phase-count groups on streams of
  * their own, forked from and joined back to the batch's stream (parallel
- * branches of a captured graph).  The states are bitwise the same in every
- * mode.  Drops a captured graph; LBF_EINVAL for unknown flags or a grid that
+ * branches of a captured graph); the batched reverse steps
+ * (lbf_batch_adjoint_step) follow it too.  The states and gradients are
+ * bitwise the same in every mode.  Drops a captured graph; LBF_EINVAL for unknown flags or a grid that
  * is negative or not a multiple of 8, LBF_EDEVICE if the side streams
  * cannot be created. */
 #define LBF_BATCH_PERSISTENT 1u

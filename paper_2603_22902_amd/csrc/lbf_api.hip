@@ -1455,15 +1455,29 @@ lbf_status lbf_batch_adjoint_step(lbf_batch_adj* ba, const void* state, const vo
   lbf_ctx* c0 = b->first;
   if (!ba->seeded) return fail(c0, LBF_ESTATE, "lbf_batch_adjoint_seed has not been called");
   if (!state || !next) return fail(c0, LBF_EINVAL, "state and next must be packed batch states");
+  // the phase-count groups on parallel branches, as in batch_launch
+  int ngroup = 0;
+  for (int gi = 0; gi < lbf::MAXP; ++gi) ngroup += ba->g[gi].n > 0;
+  const bool conc = (b->launch & LBF_BATCH_CONCURRENT) && ngroup > 1;
+  if (conc) HIPCHK(c0, hipEventRecord(b->fork, b->stream), "hipEventRecord");
+  bool first = true;
   for (int gi = 0; gi < lbf::MAXP; ++gi) {
     const lbf_batch_adj::Group& G = ba->g[gi];
     if (!G.n) continue;
     const lbf::Ops* ops = b->g[gi].ctx[0]->ops;
+    const bool side = conc && !first;
+    hipStream_t s = side ? b->side[gi] : b->stream;
+    first = false;
+    if (side) HIPCHK(c0, hipStreamWaitEvent(s, b->fork, 0), "hipStreamWaitEvent");
     const int nb0 = lbf::collide_reverse_tiled(gi + 1) ? G.tblocks : G.cblocks;
-    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, nb0, state, next, ba->cur, ba->base, b->stream),
+    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, nb0, state, next, ba->cur, ba->base, s),
            "batched collide reverse");
-    HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, ba->base, b->stream),
+    HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, ba->base, s),
            "batched gather");
+    if (side) {
+      HIPCHK(c0, hipEventRecord(b->join[gi], s), "hipEventRecord");
+      HIPCHK(c0, hipStreamWaitEvent(b->stream, b->join[gi], 0), "hipStreamWaitEvent");
+    }
   }
   ba->cur ^= 1;
   for (lbf_adj* a : ba->adj) a->cur = ba->cur;

@@ -316,6 +316,23 @@ def test_batched_adjoint_through_graph_replays():
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
 
 
+def test_batched_adjoint_in_each_launch_mode():
+    """The reverse steps with the phase-count groups on one stream and on
+    concurrent branches (the default) give the same batched gradient."""
+    from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
+    cases = _adj_cases("fp32")
+    assert len({c["params"]["nphase"] for c in cases}) > 1, "the cases must span phase counts"
+    n, window = 12, 4
+    res = []
+    for concurrent in (False, True):
+        b = Batch(_solvers(cases))
+        b.set_launch(concurrent=concurrent)
+        ck = batch_forward_with_checkpoints(b, n, window)
+        res.append(batch_reverse_sweep(b, ck, n, window))
+        b.close()
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+
+
 def test_batched_adjoint_argument_errors():
     """Refusals on the host, before any launch: adjoint step before seed,
     a missing next state, unaligned or aliased packed states, an unknown
