@@ -161,12 +161,18 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
   gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, part + (long long)t * NPAR);
 }
 
-// Which form the collide reverse takes: for N >= 3 the tiled layer march
-// below (fewer live registers than reading every neighbour's fields from
-// global memory); for N <= 2 one thread per cell, which fits in 256 VGPRs
-// without spilling where the tiled form spills.  The batched kernels follow
-// the same rule, so batched and single-case sweeps stay bitwise equal.
-constexpr bool collide_reverse_tiled(int NP) { return NP >= 3; }
+// Which form the collide reverse takes, from the phase count and the number
+// of tiles of the step geometry: for N >= 3 the tiled layer march below
+// (fewer live registers than reading every neighbour's fields from global
+// memory); for N = 2 the tiled form once the grid has TILED2_MIN_TILES tiles
+// (about 512² cells), where it is faster; below that its blocks underfill the
+// GPU and one thread per cell is faster; for N = 1 one thread per cell.  The
+// batched kernels apply the same rule to each case, so batched and
+// single-case sweeps stay bitwise equal.
+constexpr long long TILED2_MIN_TILES = 512;
+constexpr bool collide_reverse_tiled(int NP, long long tiles) {
+  return NP >= 3 || (NP == 2 && tiles >= TILED2_MIN_TILES);
+}
 
 template <class C>
 __global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
@@ -338,9 +344,11 @@ inline hipError_t launch_adjoint(int pass, const S* pin, const S* ain, const S* 
   switch (pass) {
     case 0: hipLaunchKernelGGL((adj_moment_kernel<C>), grid, block, 0, s, a, dP); break;
     case 1:
-      if constexpr (!collide_reverse_tiled(NP)) {
-        hipLaunchKernelGGL((adj_collide_kernel<C>), grid, block, 0, s, a, dP, part);
-        break;
+      if constexpr (NP <= 2) {
+        if (!collide_reverse_tiled(NP, step_geometry<C>(P).nblocks)) {
+          hipLaunchKernelGGL((adj_collide_kernel<C>), grid, block, 0, s, a, dP, part);
+          break;
+        }
       }
       [[fallthrough]];
     case 2: {

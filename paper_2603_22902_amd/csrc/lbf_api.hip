@@ -1287,7 +1287,7 @@ struct lbf_batch_adj {
   std::vector<lbf_adj*> adj;  // caller order
   struct Group {
     size_t off;  // case table offset in the device buffer
-    int n, cblocks, tblocks;
+    int n, cblocks, tblocks, ctblocks;  // blocks of the per-cell collide reverse, the gather, the tiled collide reverse
   } g[lbf::MAXP];
   int cur;
   bool seeded;
@@ -1365,7 +1365,7 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
     lbf_batch_adj::Group& G = ba->g[gi];
     G.off = toff[gi];
     G.n = (int)g.ctx.size();
-    G.cblocks = G.tblocks = 0;
+    G.cblocks = G.tblocks = G.ctblocks = 0;
     if (g.ctx.empty()) continue;
     std::vector<lbf::BatchAdjCase> t(g.ctx.size());
     std::vector<lbf::KParams> kps(g.ctx.size());
@@ -1394,11 +1394,6 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
       }
       bc.work_off = static_cast<char*>(adj_work(a)) - ba->base;
       bc.part_off = reinterpret_cast<char*>(adj_part(a)) - ba->base;
-      // the single-case grids: one thread per cell for the collide reverse,
-      // the step geometry for the tiled gather
-      bc.cblocks = a->lay.cblocks;
-      bc.first_cblock = G.cblocks;
-      G.cblocks += bc.cblocks;
       // the single-case tile geometry, which the gradient rows follow
       const lbf::Geometry geo = c->prm.precision == LBF_FP64
                                     ? lbf::step_geometry<lbf::CfgOf<2, 1, double, double>>(c->kp)
@@ -1409,6 +1404,15 @@ lbf_status lbf_batch_adjoint_create(lbf_batch* b, void* dev_buf, size_t bytes, l
       bc.nblocks = geo.nblocks;
       bc.first_tblock = G.tblocks;
       G.tblocks += bc.nblocks;
+      // the single-case form of the collide reverse: one thread per cell
+      // (256-cell blocks) or the tiles of the step geometry
+      const bool tiled = lbf::collide_reverse_tiled(c->N, geo.nblocks);
+      bc.cblocks = tiled ? 0 : a->lay.cblocks;
+      bc.first_cblock = G.cblocks;
+      G.cblocks += bc.cblocks;
+      bc.ctblocks = tiled ? geo.nblocks : 0;
+      bc.first_ctblock = G.ctblocks;
+      G.ctblocks += bc.ctblocks;
     }
     hipError_t e = hipMemcpyAsync(ba->base + G.off, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice,
                                   b->stream);
@@ -1469,9 +1473,12 @@ lbf_status lbf_batch_adjoint_step(lbf_batch_adj* ba, const void* state, const vo
     hipStream_t s = side ? b->side[gi] : b->stream;
     first = false;
     if (side) HIPCHK(c0, hipStreamWaitEvent(s, b->fork, 0), "hipStreamWaitEvent");
-    const int nb0 = lbf::collide_reverse_tiled(gi + 1) ? G.tblocks : G.cblocks;
-    HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, nb0, state, next, ba->cur, ba->base, s),
-           "batched collide reverse");
+    if (G.cblocks)
+      HIPCHK(c0, ops->batch_adjoint(0, ba->base + G.off, G.n, G.cblocks, state, next, ba->cur, ba->base, s),
+             "batched collide reverse (per cell)");
+    if (G.ctblocks)
+      HIPCHK(c0, ops->batch_adjoint(2, ba->base + G.off, G.n, G.ctblocks, state, next, ba->cur, ba->base, s),
+             "batched collide reverse (tiled)");
     HIPCHK(c0, ops->batch_adjoint(1, ba->base + G.off, G.n, G.tblocks, state, next, ba->cur, ba->base, s),
            "batched gather");
     if (side) {

@@ -26,17 +26,25 @@ struct BatchAdjCase {
   long long soff, pop_bytes;
   long long lp_off[2], la_off[2], work_off;
   long long part_off;                 // gradient rows of the case
-  int cblocks, first_cblock;          // one-thread-per-cell grid (collide reverse for N <= 2)
+  int cblocks, first_cblock;          // one-thread-per-cell collide reverse (0 where the case takes the tiled one)
   int ntx, nty, chunk, nblocks;       // tile geometry of both passes (single-case step geometry)
-  int first_tblock;
+  int first_tblock;                   // the tiled gather, every case
+  int ctblocks, first_ctblock;        // tiled collide reverse (nblocks where the case takes it, else 0)
 };
 
-// Last case k with first[k] <= b (uniform across the block).
-__device__ inline int batch_adj_case(const BatchAdjCase* cs, int ncase, int b, bool collide) {
+// Which block-number range a pass's blocks count in.
+enum BatchAdjRange { ADJ_CELLS = 0, ADJ_TILES = 1, ADJ_COLLIDE_TILES = 2 };
+
+// Last case k with first[k] <= b (uniform across the block).  A case with
+// no blocks in the range shares its first block with the next case, so the
+// search never lands on it.
+__device__ inline int batch_adj_case(const BatchAdjCase* cs, int ncase, int b, int range) {
   int lo = 0, hi = ncase - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int f = collide ? cs[mid].first_cblock : cs[mid].first_tblock;
+    const int f = range == ADJ_CELLS ? cs[mid].first_cblock
+                  : range == ADJ_TILES ? cs[mid].first_tblock
+                                       : cs[mid].first_ctblock;
     if (f <= b)
       lo = mid;
     else
@@ -72,7 +80,7 @@ __global__ void __launch_bounds__(ADJ_THREADS) __attribute__((amdgpu_waves_per_e
     batch_adj_collide_cell_kernel(const BatchAdjCase* __restrict__ cs, const KParams* __restrict__ kpa, int ncase,
                                   const char* __restrict__ state, const char* __restrict__ next, int parity,
                                   char* __restrict__ abase) {
-  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, blockIdx.x, true));
+  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, blockIdx.x, ADJ_CELLS));
   const BatchAdjCase& bc = cs[k];
   const KParams& P = kpa[k];
   const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity, abase);
@@ -92,12 +100,12 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(2)))
                              int parity, char* __restrict__ abase) {
   __shared__ Smem<C> sm;
   const int Lg = xcd_remap(blockIdx.x, nblocks);
-  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, false));
+  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, ADJ_COLLIDE_TILES));
   const BatchAdjCase& bc = cs[k];
   const KParams& P = kpa[k];
   const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity, abase);
   const StepArgs<typename C::S> sa = fill_args<C>(a, bc.ntx, bc.nty, bc.chunk, bc.nblocks);
-  const int t = Lg - bc.first_tblock;
+  const int t = Lg - bc.first_ctblock;
   collide_tile_block<C>(a, sa, P, block_pos_local<C>(sa, P, t), sm, batch_adj_part(bc, abase) + (long long)t * NPAR);
 }
 
@@ -108,7 +116,7 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
                             int parity, char* __restrict__ abase) {
   __shared__ FdaRing<C> ring;
   const int Lg = xcd_remap(blockIdx.x, nblocks);
-  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, false));
+  const int k = __builtin_amdgcn_readfirstlane(batch_adj_case(cs, ncase, Lg, ADJ_TILES));
   const BatchAdjCase& bc = cs[k];
   const KParams& P = kpa[k];
   const AdjArgs<C> a = batch_adj_args<C>(bc, state, next, parity, abase);
@@ -121,12 +129,14 @@ __global__ void __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(4)))
   gather_tile_block<C>(a, P, block_pos_local<C>(sa, P, t), ring, batch_adj_part(bc, abase) + (long long)t * NPAR);
 }
 
-// pass 0: collide reverse (over the cases' tiles for N >= 3, their 256-cell
-// blocks for N <= 2), 1: tiled gather over the cases' tiles; nblocks in
-// all.  cases: the case table followed, at the next 256-byte
-// boundary, by the cases' parameter blocks in table order, which the kernels
-// read through a restrict pointer (scalar loads, no LDS copy).  abase: the
-// batched adjoint buffer the table's offsets count from.
+// pass 0: one-thread-per-cell collide reverse over the 256-cell blocks of
+// the cases that take it (N <= 2), 2: tiled collide reverse over the tiles
+// of the cases that take it, 1: tiled gather over every case's tiles
+// (collide_reverse_tiled decides per case); nblocks in all.  cases: the
+// case table followed, at the next 256-byte boundary, by the cases'
+// parameter blocks in table order, which the kernels read through a
+// restrict pointer (scalar loads, no LDS copy).  abase: the batched adjoint
+// buffer the table's offsets count from.
 inline size_t batch_adj_params_offset(int ncase) {
   return ((size_t)ncase * sizeof(BatchAdjCase) + 255) & ~size_t(255);
 }
@@ -142,13 +152,19 @@ inline hipError_t launch_batch_adjoint(int pass, const void* cases, int ncase, i
   const char* nx = static_cast<const char*>(next);
   char* ab = static_cast<char*>(abase);
   if (!st || !nx || !ab || nblocks < 1) return hipErrorInvalidValue;
-  if (pass == 0 && !collide_reverse_tiled(NP))
-    hipLaunchKernelGGL((batch_adj_collide_cell_kernel<C>), dim3(nblocks), dim3(ADJ_THREADS), 0, s, cs, kpa, ncase,
-                       st, nx, parity, ab);
-  else if (pass == 0)
-    hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
-                       nx, parity, ab);
-  else if (pass == 1)
+  if (pass == 0) {
+    if constexpr (NP <= 2)
+      hipLaunchKernelGGL((batch_adj_collide_cell_kernel<C>), dim3(nblocks), dim3(ADJ_THREADS), 0, s, cs, kpa,
+                         ncase, st, nx, parity, ab);
+    else
+      return hipErrorInvalidValue;
+  } else if (pass == 2) {
+    if constexpr (NP >= 2)
+      hipLaunchKernelGGL((batch_adj_collide_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks,
+                         st, nx, parity, ab);
+    else
+      return hipErrorInvalidValue;
+  } else if (pass == 1)
     hipLaunchKernelGGL((batch_adj_gather_kernel<C>), dim3(nblocks), dim3(C::NT), 0, s, cs, kpa, ncase, nblocks, st,
                        nx, parity, ab);
   else

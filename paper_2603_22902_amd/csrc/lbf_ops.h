@@ -34,8 +34,9 @@ struct Ops {
   // (lbf_batch.h batch_grid).
   hipError_t (*batch)(int pass, int variant, const void* cases, int ncase, int nblocks, int parity,
                       const void* src, void* dst, bool packed, int grid, hipStream_t s);
-  // Batched reverse-step passes (lbf_batch_adjoint.h): pass 0 collide
-  // reverse, 1 tiled gather; NULL where the adjoint is not built.
+  // Batched reverse-step passes (lbf_batch_adjoint.h): pass 0 per-cell
+  // collide reverse, 2 tiled collide reverse, 1 tiled gather; NULL where the
+  // adjoint is not built.
   hipError_t (*batch_adjoint)(int pass, const void* cases, int ncase, int nblocks, const void* state,
                               const void* next, int parity, void* abase, hipStream_t s);
 };

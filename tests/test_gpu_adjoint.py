@@ -75,6 +75,20 @@ def test_gpu_adjoint_matches_emulator_across_tiles(N):
     assert np.abs(g["raw"] - ge).max() <= 1e-10 * np.abs(ge).max(), (g["raw"], ge)
 
 
+def test_gpu_two_phase_tiled_reverse_matches_emulator():
+    """130 x 1024: 2 x 512 = 1 024 tiles of the step geometry, past the
+    count from which two phases take the tiled collide reverse (below it,
+    one thread per cell).  The GPU sweep against the host emulator of the
+    same passes, float64, within 1e-10 of the gradient's scale."""
+    spec = (2, ("wall", "open"), ("dirichlet", "dirichlet"), 70.0)
+    case = make_case(*spec, shape=(130, 1024))
+    print("two-phase tiled reverse", spec, flush=True)
+    J, g = _grad(case, 6, 6)
+    Je, ge = emulator.adjoint(case["params"], case["phi"], case["T"], 6)
+    assert abs(J - Je) <= 1e-13
+    assert np.abs(g["raw"] - ge).max() <= 1e-10 * np.abs(ge).max(), (g["raw"], ge)
+
+
 def test_gpu_front_gradient_matches_emulator_and_oracle():
     """The front-position objective (sum f_s psi per wall-layer cell): the
     float64 sweep against the emulator, and against central differences of

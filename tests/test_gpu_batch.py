@@ -401,9 +401,9 @@ def test_ragged_batch_of_every_phase_count_equals_single_steps(precision):
 
 @pytest.mark.parametrize("precision,objective", [("fp64", "frozen_fraction"), ("fp32", "front")])
 def test_ragged_batched_adjoint_of_every_phase_count(precision, objective):
-    """The batched reverse sweep over phase counts 1 to 4 (per-cell collide
-    reverse for N <= 2, tiled for N >= 3) on ragged sides gives every case
-    bitwise the objective and gradient of its single-case sweep."""
+    """The batched reverse sweep over phase counts 1 to 4 (each case's
+    collide reverse in its single-case form) on ragged sides gives every
+    case bitwise the objective and gradient of its single-case sweep."""
     from paper_2603_22902_amd.adjoint import frozen_fraction_and_gradient
     from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
     cases = _ragged_cases(precision)
@@ -415,6 +415,31 @@ def test_ragged_batched_adjoint_of_every_phase_count(precision, objective):
     assert np.all(np.isfinite(g)) and np.all(J > 0.0)
     for k, c in enumerate(cases):
         Jk, gk = frozen_fraction_and_gradient(c, n, window, objective=objective)
+        assert J[k] == Jk, (k, J[k], Jk)
+        assert np.array_equal(g[k], gk["raw"]), (k, g[k], gk["raw"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_adjoint_mixes_two_phase_reverse_forms(precision):
+    """Two-phase cases on both sides of the tile count from which the
+    collide reverse is tiled (130 x 1024: 1 024 tiles; the others one thread
+    per cell) and a three-phase case in one batch: each gives bitwise the
+    objective and gradient of its single-case sweep."""
+    from paper_2603_22902_amd.adjoint import frozen_fraction_and_gradient
+    from paper_2603_22902_amd.batch import Batch, batch_forward_with_checkpoints, batch_reverse_sweep
+    specs = [((97, 33), 2), ((130, 1024), 2), ((64, 40), 2), ((130, 19), 3)]
+    cases = [synth.near_melting(synth.small(dim=2, shape=shape, nphase=N, precision=precision,
+                                            flow_bc=("wall", "open"), therm_bc=("dirichlet", "adiabatic"),
+                                            theta_deg=70.0))
+             for shape, N in specs]
+    n, window = 8, 3
+    print("mixed two-phase reverse forms", precision, flush=True)
+    b = Batch(_solvers(cases))
+    ck = batch_forward_with_checkpoints(b, n, window)
+    J, g = batch_reverse_sweep(b, ck, n, window)
+    assert np.all(np.isfinite(g)) and np.all(J > 0.0)
+    for k, c in enumerate(cases):
+        Jk, gk = frozen_fraction_and_gradient(c, n, window)
         assert J[k] == Jk, (k, J[k], Jk)
         assert np.array_equal(g[k], gk["raw"]), (k, g[k], gk["raw"])
 
