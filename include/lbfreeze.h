@@ -296,9 +296,9 @@ lbf_status lbf_batch_tune(lbf_batch* b, int trial_steps, int* tile);
  * their own, forked from and joined back to the batch's stream (parallel
  * branches of a captured graph); the batched reverse steps
  * (lbf_batch_adjoint_step) follow it too.  The states and gradients are
- * bitwise the same in every mode.  Drops a captured graph; LBF_EINVAL for unknown flags or a grid that
- * is negative or not a multiple of 8, LBF_EDEVICE if the side streams
- * cannot be created. */
+ * bitwise the same in every mode.  Drops a captured graph; LBF_EINVAL for
+ * unknown flags or a grid that is negative or not a multiple of 8,
+ * LBF_EDEVICE if the side streams cannot be created. */
 #define LBF_BATCH_PERSISTENT 1u
 #define LBF_BATCH_CONCURRENT 2u
 lbf_status lbf_batch_set_launch(lbf_batch* b, unsigned flags, int grid);
