@@ -390,6 +390,13 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, c
   const ST* __restrict__ pin = a.pin;
   const ST* __restrict__ ain = a.ain;
   ST* __restrict__ pout = a.pout;
+  // The flow populations (step 5) are loaded first, so that their latency
+  // overlaps the LDS reads and arithmetic of the finite differences.
+  R fpop[Q];
+  if (!MOMENTS) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fpop[i] = R(plane(pin, i, nc)[cell]);
+  }
 
   // Own moments (identical to the values the neighbours see).
   R phi[NP];
@@ -517,10 +524,11 @@ __host__ __device__ inline void process_cell(const StepArgs<typename C::S>& a, c
     F[d] = fsd + rho * R(P.grav[d]);
   }
 
-  // Step 5: flow macros.
-  R fpop[Q];
+  // Step 5: flow macros (the moments mode loads the flow populations here).
+  if (MOMENTS) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) fpop[i] = R(plane(pin, i, nc)[cell]);
+    for (int i = 0; i < Q; ++i) fpop[i] = R(plane(pin, i, nc)[cell]);
+  }
   R mom[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) mom[d] = R(0);
