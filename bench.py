@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS of coupled LB step + % HBM roofline; adjoint/forward cost ratio"
-KERNEL_SOURCES = ["lbf_step.h", "lbf_kernels.h", "lbf_lattice.h", "lbf_kernels_f32_moments.hip"]
+KERNEL_SOURCES = ["lbf_step.h", "lbf_kernels.h", "lbf_lattice.h", "lbf_kernels_f32_ilp.hip"]
 
 
 def kernel_hash() -> str:

@@ -47,7 +47,7 @@ def _run(cmd, verbose):
 def build(verbose: bool = False, emulator: bool = True) -> str:
     with tempfile.TemporaryDirectory(prefix="lbf_build_") as tmp:
         units = [("lbf_api.hip", []), ("lbf_kernels_f32.hip", []),
-                 ("lbf_kernels_f32_moments.hip", ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]),
+                 ("lbf_kernels_f32_ilp.hip", ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]),
                  ("lbf_kernels_f64.hip", ["-ffp-contract=off"]), ("lbf_kernels_mix.hip", [])]
         objs = []
         jobs = []
